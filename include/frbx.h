@@ -1,0 +1,250 @@
+/*
+ * frbx -- cross-spectrum fast-radio-burst search on AMD MI355X (gfx950).
+ *
+ * C ABI of libfrbx.so.  The method is that of Liu et al. 2018, "A Fast Radio
+ * Burst Search Method for VLBI Observation" (arXiv:1801.02391): per-baseline
+ * incoherent dedispersion of millisecond complex cross spectra over a grid of
+ * DM trials (Sec. 2.2, Eqs. 1-3), a fringe search of every half-overlapped
+ * time segment over single-band delay, multiband delay and delay rate
+ * (Sec. 2.3, Eqs. 4-5; Sec. 5.1), normalisation and threshold of each
+ * baseline's power series (Eq. 6, Sec. 2.4.1), the multi-window filter,
+ * best-DM selection (Sec. 5.3) and cross-baseline matching (Sec. 2.4.1).
+ *
+ * Conventions used by every entry point
+ *   Units: MHz, ms, microseconds (MHz * us = cycles), pc cm^-3; rates in s/s.
+ *   Arrays are row-major; "[A][B]" means A is the slowest index.
+ *   Every call returns frbx_status and never throws.  On failure the context
+ *   (when there is one) keeps a message readable with frbx_last_error().
+ *   Output buffers are owned by the caller.  A call taking (cap, *n) writes at
+ *   most cap records, sets *n to the number available and returns
+ *   FRBX_E_RANGE when cap < *n (cap = 0 is a size query).
+ *   One context belongs to one host thread and one HIP stream.
+ *   No entry point allocates device memory except frbx_create/frbx_load/
+ *   frbx_run (which size their workspaces) and none frees memory the caller
+ *   owns.
+ */
+#ifndef FRBX_H
+#define FRBX_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct frbx_ctx frbx_ctx;
+
+typedef enum {
+  FRBX_OK = 0,
+  FRBX_E_INVAL = 1,  /* an argument or a grid is invalid                    */
+  FRBX_E_STATE = 2,  /* call out of order (e.g. results before frbx_run)     */
+  FRBX_E_RANGE = 3,  /* output capacity too small; *n holds the size needed  */
+  FRBX_E_NOMEM = 4,  /* an allocation failed                                 */
+  FRBX_E_DEVICE = 5  /* a HIP runtime call or a kernel launch failed         */
+} frbx_status;
+
+/* Data layout of the cross spectra S(n, j, k) of Sec. 2.2: IF n in [0, N)
+ * with sky frequency if_freq_mhz[n] (lower edge, upper sideband), frequency
+ * point j in [0, J) at baseband frequency j * chan_bw_mhz, accumulation
+ * period (AP) k in [0, K) of t_ap_ms.  The pointer is read during
+ * frbx_create only. */
+typedef struct {
+  int32_t n_baselines;        /* B >= 1                          */
+  int32_t n_if;               /* N >= 1                          */
+  int32_t n_chan;             /* J: 8, 16, 32, 64, 128 or 256    */
+  int64_t n_frames;           /* K >= 1                          */
+  double t_ap_ms;             /* AP duration, > 0                */
+  double chan_bw_mhz;         /* frequency-point spacing, > 0    */
+  const double *if_freq_mhz;  /* [N] IF sky frequencies          */
+} frbx_layout;
+
+/* One record per threshold crossing (Sec. 2.4.1 step a) or per single-pulse
+ * detection (steps b-d and Sec. 5.3).  k0 is the first AP of the segment on
+ * the dedispersion reference frequency (the top of the band); the segment
+ * covers APs [k0, k0 + window_len - 1]. */
+typedef struct {
+  int32_t baseline;
+  int32_t dm_index;
+  int32_t window_index;
+  int32_t window_len;
+  int64_t segment;      /* q: k0 = q * hop                                  */
+  int64_t k0;
+  double dm;            /* pc cm^-3                                         */
+  double power;         /* |G| at the peak (Eq. 5 amplitude)               */
+  double power_norm;    /* Eq. 6                                            */
+  int32_t rate_idx;     /* r: rate = (r - R/2) * rate_step                  */
+  int32_t sbd_idx;      /* s: sbd  = (s - PJ/2) / (PJ * chan_bw)            */
+  int32_t mbd_idx;      /* m: mbd  = (m - M/2) * mbd_step                   */
+  int32_t n_windows;    /* detections: distinct windows in its group, else 0 */
+  double rate;          /* s/s                                              */
+  double sbd_us;
+  double mbd_us;
+  int32_t group_id;     /* detections: cross-baseline group, else -1        */
+  int32_t reserved;
+} frbx_candidate;
+
+/* Cross-baseline matching group (Sec. 2.4.1, cross matching). */
+typedef struct {
+  int32_t group_id;
+  int32_t n_baselines;  /* distinct baselines among its detections          */
+  int64_t k_start;      /* earliest AP covered by a member                  */
+  int64_t k_end;        /* latest AP covered by a member                    */
+  int32_t best;         /* index (into the detection list) of the member
+                           with the highest normalised power               */
+  int32_t reported;     /* n_baselines >= n_bl_min                          */
+} frbx_group;
+
+/* Library version string (static storage). */
+const char *frbx_version(void);
+
+/* Create a search context on HIP device `device`, bound to `hip_stream`
+ * (a hipStream_t; NULL = the device's null stream).  Validates the layout;
+ * FRBX_E_INVAL for an unsupported shape, FRBX_E_DEVICE if the device cannot
+ * be selected.  Default grids: one DM trial at 0, sbd_pad 4, M = 256 on the
+ * default lattice, R = 1, windows {2, 4}, threshold 3, N_win,min 3,
+ * N_bl,min 2. */
+frbx_status frbx_create(const frbx_layout *layout, int device, void *hip_stream,
+                        frbx_ctx **out);
+
+/* Release every resource of the context (NULL is ignored). */
+void frbx_destroy(frbx_ctx *ctx);
+
+/* Text of the last error on this context (empty if none). */
+const char *frbx_last_error(const frbx_ctx *ctx);
+
+/* Channel-delay and initial-phase calibration of Eq. 5 (Sec. 2.3): every
+ * point is rotated by exp(-i [2 pi (f_j - f_bw/2) tau0 + phi0]) with
+ * f_bw = J * chan_bw before the fit.  tau0_us, phi0_rad: [B][N] host
+ * arrays (NULL = zeros). */
+frbx_status frbx_set_calibration(frbx_ctx *ctx, const double *tau0_us, const double *phi0_rad);
+
+/* DM trials DM_d = dm_lo + d * dm_step, d in [0, n_dm) (coarse DM bins of
+ * Sec. 5.3).  k_dm: dispersion constant of Eq. 1 in ms MHz^2 (<= 0 selects
+ * 4.149e6).  The AP offsets follow Eqs. 1-2 with the reference at the highest
+ * channel frequency. */
+frbx_status frbx_set_dm_grid(frbx_ctx *ctx, double dm_lo, double dm_step, int32_t n_dm,
+                             double k_dm);
+
+/* Delay grids of the fringe search (Eq. 5, Sec. 5.1).  SBD: PJ = sbd_pad * J
+ * points, sbd_pad in {1, 2, 4, 8}.  MBD: n_mbd in {16, 32, 64, 128, 256}
+ * points of step mbd_step_us; mbd_step_us <= 0 selects T/M with T = 1/g the
+ * MBD ambiguity, g the gcd of the IF offsets from IF 0 in whole kHz.  Any
+ * step must place every IF on the transform lattice (f0^n - f0^0) * step * M
+ * integral, distinct modulo M; FRBX_E_INVAL otherwise.  f_ref_fit_mhz is the
+ * fit reference frequency (NaN = f0^0); it only rotates the phase of G. */
+frbx_status frbx_set_delay_grid(frbx_ctx *ctx, int32_t sbd_pad, int32_t n_mbd,
+                                double mbd_step_us, double f_ref_fit_mhz);
+
+/* Delay-rate bins of Eq. 4: rate_r = (r - floor(R/2)) * rate_step, R in
+ * [1, 64].  rate_step <= 0 selects 1 / (2 f_max l_max t_ap) (half the
+ * fringe-rate resolution of the longest window at the top frequency).  The
+ * rate phase is taken about the window centre of the dedispersed APs. */
+frbx_status frbx_set_rate_grid(frbx_ctx *ctx, int32_t n_rate, double rate_step);
+
+/* Window lengths in APs (Sec. 2.4.1), 1 <= n <= 8, distinct, each >= 1.
+ * Segments of window l start every hop = max(1, l/2) APs. */
+frbx_status frbx_set_windows(frbx_ctx *ctx, const int32_t *len_frames, int32_t n);
+
+/* Detection parameters: threshold on the Eq. 6 normalised power (strict >),
+ * minimum number of windows per single pulse (step d) and of baselines per
+ * reported cross-matching group. */
+frbx_status frbx_set_detection(frbx_ctx *ctx, double threshold, int32_t n_win_min,
+                               int32_t n_bl_min);
+
+/* Hand the cross spectra to the context: complex64 (re, im float32 pairs)
+ * with layout [B][N][J][K].  is_device = 1: `vis` is a device pointer on the
+ * context's device; it is borrowed and must stay valid and unchanged until
+ * the next frbx_load or frbx_destroy.  is_device = 0: host memory, copied. */
+frbx_status frbx_load(frbx_ctx *ctx, const void *vis, int is_device);
+
+/* Run the whole search on the context's stream and wait for it: dedispersion
+ * and segment sums, fringe search and peak of every (baseline, DM trial,
+ * window, segment), Eq. 6 statistics and threshold on the device; the
+ * multi-window filter, best-DM merge and cross-baseline matching on the
+ * host. */
+frbx_status frbx_run(frbx_ctx *ctx);
+
+/* Segment layout of the current grids: dk_max (largest AP offset over all DM
+ * trials), per window its hop and segment count Q (arrays of the number of
+ * windows, may be NULL), and cube_len = sum of Q (segments per (b, d)). */
+frbx_status frbx_get_segments(const frbx_ctx *ctx, int64_t *dk_max, int32_t *hop,
+                              int64_t *n_seg, int64_t *cube_len);
+
+/* AP offsets of Eq. 2 for the current DM grid: [D][N][J] int32 (host). */
+frbx_status frbx_get_ap_offsets(const frbx_ctx *ctx, int32_t *out, int64_t cap, int64_t *n);
+
+/* Power cube: power[b][d][seg] = max |G| of the segment and idx = packed
+ * (r * PJ + s) * M + m of its lowest-index maximum; seg runs over the windows
+ * in order, each window's segments consecutive.  Host buffers, cap in
+ * elements; either pointer may be NULL. */
+frbx_status frbx_get_power_cube(const frbx_ctx *ctx, float *power, int32_t *idx,
+                                int64_t cap, int64_t *n);
+
+/* Device pointers of the power cube (valid until the next run/destroy). */
+frbx_status frbx_get_power_cube_device(const frbx_ctx *ctx, const float **power,
+                                       const int32_t **idx);
+
+/* Eq. 6 statistics per (b, d, window): mean, population std and the number
+ * of finite segment powers they were taken over. */
+frbx_status frbx_get_stats(const frbx_ctx *ctx, double *mean, double *stdev,
+                           int64_t *count, int64_t cap, int64_t *n);
+
+/* Threshold crossings (Sec. 2.4.1 step a), sorted by (b, d, window, q). */
+frbx_status frbx_get_crossings(const frbx_ctx *ctx, frbx_candidate *out, int64_t cap,
+                               int64_t *n);
+
+/* Single-pulse detections after steps b-d and the best-DM merge, ordered by
+ * (baseline, k0); group_id names their cross-matching group. */
+frbx_status frbx_get_candidates(const frbx_ctx *ctx, frbx_candidate *out, int64_t cap,
+                                int64_t *n);
+
+/* Cross-matching groups (all of them; `reported` marks n_baselines >=
+ * N_bl,min), in creation order. */
+frbx_status frbx_get_groups(const frbx_ctx *ctx, frbx_group *out, int64_t cap, int64_t *n);
+
+/* |G|^2 of every cell of one segment, [R][PJ][M] float32 into a device
+ * buffer of the caller (for element-wise checks of the fringe transform;
+ * needs a loaded context with valid grids). */
+frbx_status frbx_dump_segment(frbx_ctx *ctx, int32_t baseline, int32_t dm_index,
+                              int32_t window_index, int64_t segment, float *dev_out);
+
+/* Per-kernel timing of the last frbx_run, from HIP events recorded on the
+ * context's stream around every launch (enable before the run; enabling adds
+ * two event records per launch).  Times in milliseconds, summed over the
+ * launches of each kernel; n_* are the launch counts and *_units the
+ * segments (fringe) or dedispersed spectra (dedisperse) they processed. */
+typedef struct {
+  double fringe_ms;
+  int64_t n_fringe;
+  int64_t fringe_units;
+  double dedisperse_ms;
+  int64_t n_dedisperse;
+  int64_t dedisperse_units;
+  double stats_ms;
+  int64_t n_stats;
+} frbx_timing;
+
+frbx_status frbx_set_timing(frbx_ctx *ctx, int enable);
+frbx_status frbx_get_timing(const frbx_ctx *ctx, frbx_timing *out);
+
+/* Host-only: the Eq. 2 AP-offset table for a layout and DM grid, [D][N][J]
+ * int32; needs no device. */
+frbx_status frbx_ap_offsets(const frbx_layout *layout, double dm_lo, double dm_step,
+                            int32_t n_dm, double k_dm, int32_t *out);
+
+/* Host-only: steps b-d per (baseline, DM), the best-DM merge and the
+ * cross-baseline matching of Sec. 2.4.1 over a list of crossings (fields
+ * baseline, dm_index, window_len, k0, power_norm, mbd_us are read; the rest
+ * is carried).  t_amb_us is the MBD ambiguity.  use_mbd = 0 skips step c
+ * (the power-summation scheme, Sec. 2.4.2).  Outputs as for
+ * frbx_get_candidates / frbx_get_groups. */
+frbx_status frbx_detect(const frbx_candidate *crossings, int64_t n_cross, double t_amb_us,
+                        int32_t n_win_min, int32_t n_bl_min, int32_t use_mbd,
+                        frbx_candidate *dets, int64_t det_cap, int64_t *n_dets,
+                        frbx_group *groups, int64_t group_cap, int64_t *n_groups);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* FRBX_H */

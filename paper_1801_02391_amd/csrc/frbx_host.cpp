@@ -1,0 +1,1002 @@
+// Host side of libfrbx: argument validation, the float64 tables of the
+// search (AP offsets of Eqs. 1-2, calibration phasors of Eq. 5, rate phasors
+// of Eq. 4, transform twiddles and the MBD lattice), orchestration of the
+// device kernels, and the host steps of Sec. 2.4.1 / Sec. 5.3 (multi-window
+// filter, best-DM merge, cross-baseline matching).
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <limits>
+#include <numeric>
+#include <string>
+#include <vector>
+
+#include "../../include/frbx.h"
+#include "frbx_internal.h"
+
+using frbx::DevCrossing;
+
+namespace {
+
+constexpr double kTwoPi = 6.283185307179586476925286766559;
+constexpr double kDefaultKdm = 4.149e6;  // ms MHz^2 per pc cm^-3
+
+bool pow2(int v) { return v > 0 && (v & (v - 1)) == 0; }
+
+template <typename T>
+void dfree(T *&p) {
+  if (p) hipFree(const_cast<void *>(reinterpret_cast<const void *>(p)));
+  p = nullptr;
+}
+
+}  // namespace
+
+struct frbx_ctx {
+  // layout
+  int B = 0, N = 0, J = 0;
+  int64_t K = 0;
+  double t_ap = 0, df = 0;
+  std::vector<double> f0;
+  int device = 0;
+  hipStream_t stream = nullptr;
+  std::string err;
+
+  // parameters
+  std::vector<double> tau0, phi0;  // [B*N]
+  double dm_lo = 0.0, dm_step = 1.0, k_dm = kDefaultKdm;
+  int n_dm = 1;
+  int sbd_pad = 4, n_mbd = 256;
+  double mbd_step_req = 0.0, f_ref_fit = std::numeric_limits<double>::quiet_NaN();
+  int n_rate = 1;
+  double rate_step_req = 0.0;
+  std::vector<int> windows{2, 4};
+  double threshold = 3.0;
+  int n_win_min = 3, n_bl_min = 2;
+
+  // derived tables
+  bool dirty = true;
+  std::vector<int32_t> dk;  // [D][N*J]
+  int64_t dk_max = 0, k_eff = 0;
+  std::vector<int> hop, nseg, segoff;
+  int64_t seg_total = 0;
+  double mbd_step = 0, t_amb = 0, rate_step = 0;
+  std::vector<int32_t> mbd_row;
+  std::vector<int> rate_off;
+
+  // device memory
+  const float2 *d_vis = nullptr;
+  float2 *d_vis_own = nullptr;
+  bool loaded = false;
+  int32_t *d_dk = nullptr;
+  float2 *d_cal = nullptr, *d_rate = nullptr, *d_tw_sbd = nullptr, *d_pre = nullptr,
+         *d_tw_mbd = nullptr;
+  int32_t *d_row = nullptr;
+  float2 *d_w = nullptr;
+  size_t w_cap = 0;
+  int dt = 1;
+  float *d_power = nullptr;
+  int32_t *d_pidx = nullptr;
+  size_t cube_cap = 0, pidx_cap = 0;
+  double *d_mean = nullptr, *d_sd = nullptr;
+  int64_t *d_cnt = nullptr;
+  size_t mean_cap = 0, sd_cap = 0, cnt_cap = 0;
+  DevCrossing *d_cross = nullptr;
+  unsigned long long *d_ncross = nullptr;
+  int64_t cross_cap = 0;
+  size_t w_budget = size_t(6) << 30;
+
+  // timing
+  bool timing = false;
+  std::vector<hipEvent_t> ev_pool;
+  size_t ev_used = 0;
+  struct Span { int kind; int64_t units; hipEvent_t a, b; };
+  std::vector<Span> spans;
+  frbx_timing last_timing{};
+
+  // results
+  bool have = false;
+  std::vector<double> mean, sd;
+  std::vector<int64_t> cnt;
+  std::vector<frbx_candidate> cross, dets;
+  std::vector<frbx_group> groups;
+
+  frbx_status fail(frbx_status s, const std::string &m) {
+    err = m;
+    return s;
+  }
+  frbx_status hip(hipError_t e, const char *what) {
+    if (e == hipSuccess) return FRBX_OK;
+    err = std::string(what) + ": " + hipGetErrorString(e);
+    return FRBX_E_DEVICE;
+  }
+  hipEvent_t event() {
+    if (ev_used == ev_pool.size()) {
+      hipEvent_t e = nullptr;
+      if (hipEventCreate(&e) != hipSuccess) return nullptr;
+      ev_pool.push_back(e);
+    }
+    return ev_pool[ev_used++];
+  }
+  // record the start of a timed launch; returns the span index or -1
+  int span_begin(int kind, int64_t units) {
+    if (!timing) return -1;
+    hipEvent_t a = event(), b = event();
+    if (!a || !b) return -1;
+    hipEventRecord(a, stream);
+    spans.push_back(Span{kind, units, a, b});
+    return int(spans.size()) - 1;
+  }
+  void span_end(int i) {
+    if (i >= 0) hipEventRecord(spans[i].b, stream);
+  }
+  void collect_timing() {
+    frbx_timing t{};
+    for (const Span &sp : spans) {
+      float ms = 0.f;
+      if (hipEventElapsedTime(&ms, sp.a, sp.b) != hipSuccess) continue;
+      if (sp.kind == 0) t.fringe_ms += ms, t.n_fringe++, t.fringe_units += sp.units;
+      if (sp.kind == 1) t.dedisperse_ms += ms, t.n_dedisperse++, t.dedisperse_units += sp.units;
+      if (sp.kind == 2) t.stats_ms += ms, t.n_stats++;
+    }
+    last_timing = t;
+    spans.clear();
+    ev_used = 0;
+  }
+  ~frbx_ctx() {
+    hipSetDevice(device);
+    for (hipEvent_t e : ev_pool) hipEventDestroy(e);
+    dfree(d_vis_own);
+    dfree(d_dk);
+    dfree(d_cal);
+    dfree(d_rate);
+    dfree(d_tw_sbd);
+    dfree(d_pre);
+    dfree(d_tw_mbd);
+    dfree(d_row);
+    dfree(d_w);
+    dfree(d_power);
+    dfree(d_pidx);
+    dfree(d_mean);
+    dfree(d_sd);
+    dfree(d_cnt);
+    dfree(d_cross);
+    dfree(d_ncross);
+  }
+};
+
+namespace {
+
+frbx_status check_layout(const frbx_layout *L, std::string &why) {
+  if (!L) return why = "layout is NULL", FRBX_E_INVAL;
+  if (L->n_baselines < 1 || L->n_if < 1 || L->n_frames < 1)
+    return why = "n_baselines, n_if and n_frames must be >= 1", FRBX_E_INVAL;
+  if (!(L->n_chan == 8 || L->n_chan == 16 || L->n_chan == 32 || L->n_chan == 64 ||
+        L->n_chan == 128 || L->n_chan == 256))
+    return why = "n_chan must be 8, 16, 32, 64, 128 or 256", FRBX_E_INVAL;
+  if (!(L->t_ap_ms > 0) || !(L->chan_bw_mhz > 0) || !std::isfinite(L->t_ap_ms) ||
+      !std::isfinite(L->chan_bw_mhz))
+    return why = "t_ap_ms and chan_bw_mhz must be finite and > 0", FRBX_E_INVAL;
+  if (!L->if_freq_mhz) return why = "if_freq_mhz is NULL", FRBX_E_INVAL;
+  for (int n = 0; n < L->n_if; ++n)
+    if (!(L->if_freq_mhz[n] > 0) || !std::isfinite(L->if_freq_mhz[n]))
+      return why = "IF frequencies must be finite and > 0", FRBX_E_INVAL;
+  if (int64_t(L->n_if) * L->n_chan > (1 << 20)) return why = "too many channels", FRBX_E_INVAL;
+  return FRBX_OK;
+}
+
+// Eq. 2 with Eq. 1: dk = floor(0.5 + k_dm DM (f^-2 - f_ref^-2) / t_ap); the
+// reference is the highest channel frequency (Sec. 2.2).
+void ap_offset_table(int N, int J, const double *f0, double df, double t_ap, double dm_lo,
+                     double dm_step, int n_dm, double k_dm, int32_t *out) {
+  double fr = 0.0;
+  for (int n = 0; n < N; ++n)
+    for (int j = 0; j < J; ++j) fr = std::max(fr, f0[n] + j * df);
+  for (int d = 0; d < n_dm; ++d) {
+    const double dm = dm_lo + d * dm_step;
+    for (int n = 0; n < N; ++n)
+      for (int j = 0; j < J; ++j) {
+        const double f = f0[n] + j * df;
+        const double dt = k_dm * dm * (1.0 / (f * f) - 1.0 / (fr * fr));
+        out[(int64_t(d) * N + n) * J + j] = static_cast<int32_t>(std::floor(0.5 + dt / t_ap));
+      }
+  }
+}
+
+// whole-kHz gcd of the IF offsets from IF 0 (0 when all coincide); -1 when
+// an offset is not a whole number of kHz
+int64_t offset_gcd_khz(const std::vector<double> &f0) {
+  int64_t g = 0;
+  for (double f : f0) {
+    const double x = std::fabs(f - f0[0]) * 1000.0;
+    const double r = std::nearbyint(x);
+    if (std::fabs(x - r) > 1e-6) return -1;
+    g = std::gcd(g, static_cast<int64_t>(r));
+  }
+  return g;
+}
+
+// exp(-i 2 pi x) for x in cycles, reduced to [-1/2, 1/2) first
+float2 cis_cycles(double x) {
+  const double r = x - std::nearbyint(x);
+  return make_float2(static_cast<float>(std::cos(kTwoPi * r)),
+                     static_cast<float>(-std::sin(kTwoPi * r)));
+}
+
+frbx_status prepare(frbx_ctx *c) {
+  if (!c->dirty) return FRBX_OK;
+  const int N = c->N, J = c->J, NJ = N * J, D = c->n_dm;
+  // AP offsets and segment layout (Eqs. 1-3)
+  c->dk.assign(size_t(D) * NJ, 0);
+  ap_offset_table(N, J, c->f0.data(), c->df, c->t_ap, c->dm_lo, c->dm_step, D, c->k_dm,
+                  c->dk.data());
+  int64_t mx = 0, mn = 0;
+  for (int32_t v : c->dk) mx = std::max<int64_t>(mx, v), mn = std::min<int64_t>(mn, v);
+  if (mn < 0) return c->fail(FRBX_E_INVAL, "negative AP offset (negative DM trial?)");
+  c->dk_max = mx;
+  c->k_eff = c->K - mx;
+  const int nw = int(c->windows.size());
+  c->hop.assign(nw, 0);
+  c->nseg.assign(nw, 0);
+  c->segoff.assign(nw, 0);
+  int64_t tot = 0;
+  for (int w = 0; w < nw; ++w) {
+    const int l = c->windows[w];
+    const int h = std::max(1, l / 2);
+    const int64_t span = c->K - mx - l;
+    const int64_t q = span >= 0 ? span / h + 1 : 0;
+    c->hop[w] = h;
+    c->nseg[w] = int(q);
+    c->segoff[w] = int(tot);
+    tot += q;
+  }
+  c->seg_total = tot;
+  if (tot > (int64_t(1) << 30)) return c->fail(FRBX_E_INVAL, "too many segments per DM trial");
+  // MBD lattice (Eq. 5 MBD term on a grid of M points)
+  const int M = c->n_mbd;
+  const int64_t g = offset_gcd_khz(c->f0);
+  if (g > 0)
+    c->t_amb = 1000.0 / double(g);
+  else if (g == 0)
+    c->t_amb = 1.0 / (J * c->df);
+  else if (!(c->mbd_step_req > 0))
+    return c->fail(FRBX_E_INVAL, "IF offsets are not whole kHz: give an explicit MBD step");
+  else
+    c->t_amb = c->mbd_step_req * M;
+  c->mbd_step = c->mbd_step_req > 0 ? c->mbd_step_req : c->t_amb / M;
+  c->mbd_row.assign(M, N);
+  for (int n = 0; n < N; ++n) {
+    const double x = (c->f0[n] - c->f0[0]) * c->mbd_step * M;
+    const double r = std::nearbyint(x);
+    if (std::fabs(x - r) > 1e-6)
+      return c->fail(FRBX_E_INVAL, "MBD step does not put every IF on the transform lattice");
+    int64_t qn = static_cast<int64_t>(r) % M;
+    if (qn < 0) qn += M;
+    if (c->mbd_row[qn] != N)
+      return c->fail(FRBX_E_INVAL, "two IFs fall on the same MBD lattice point: raise n_mbd");
+    c->mbd_row[qn] = n;
+  }
+  // rate grid (Eq. 4)
+  int lmax = 1;
+  for (int l : c->windows) lmax = std::max(lmax, l);
+  double fmax = 0;
+  for (int n = 0; n < N; ++n) fmax = std::max(fmax, c->f0[n] + (J - 1) * c->df);
+  c->rate_step = c->rate_step_req > 0 ? c->rate_step_req
+                                      : 1.0 / (2.0 * fmax * 1e6 * lmax * c->t_ap * 1e-3);
+  if (int64_t(c->n_rate) * c->sbd_pad * J * M >= (int64_t(1) << 31))
+    return c->fail(FRBX_E_INVAL, "rate x SBD x MBD grid too large");
+  if (!frbx::fringe_supported(J, M, N, c->sbd_pad))
+    return c->fail(FRBX_E_INVAL, "IF count too large for this channel count / grid");
+
+  hipSetDevice(c->device);
+  // device tables
+  std::vector<float2> rate;
+  c->rate_off.assign(nw, 0);
+  const int R = c->n_rate;
+  for (int w = 0; w < nw; ++w) {
+    const int l = c->windows[w];
+    c->rate_off[w] = int(rate.size());
+    for (int r = 0; r < R; ++r) {
+      const double rho = (r - R / 2) * c->rate_step;
+      for (int n = 0; n < N; ++n)
+        for (int u = 0; u < l; ++u)
+          rate.push_back(cis_cycles(1e3 * rho * c->f0[n] * c->t_ap * (u - (l - 1) / 2.0)));
+    }
+  }
+  const int PJ = c->sbd_pad * J;
+  const int JA = J >= 128 ? 16 : (J >= 32 ? 8 : 4);
+  std::vector<float2> tw_sbd(PJ), pre(size_t(c->sbd_pad) * JA), tw_mbd(M);
+  for (int k = 0; k < PJ; ++k) tw_sbd[k] = cis_cycles(double(k) / PJ);
+  for (int cc = 0; cc < c->sbd_pad; ++cc)
+    for (int i = 0; i < JA; ++i) pre[cc * JA + i] = cis_cycles(double(i * cc) / (c->sbd_pad * JA));
+  for (int k = 0; k < M; ++k) tw_mbd[k] = cis_cycles(double(k) / M);
+  // calibration phasors (Eq. 5)
+  std::vector<float2> cal(size_t(c->B) * NJ);
+  for (int b = 0; b < c->B; ++b)
+    for (int n = 0; n < N; ++n)
+      for (int j = 0; j < J; ++j) {
+        const double cyc = (j * c->df - J * c->df / 2.0) * c->tau0[b * N + n] +
+                           c->phi0[b * N + n] / kTwoPi;
+        cal[(size_t(b) * N + n) * J + j] = cis_cycles(cyc);
+      }
+  auto up = [&](auto *&dptr, const auto &vec) -> frbx_status {
+    dfree(dptr);
+    const size_t bytes = vec.size() * sizeof(vec[0]);
+    if (bytes == 0) return FRBX_OK;
+    if (hipMalloc(reinterpret_cast<void **>(&dptr), bytes) != hipSuccess)
+      return c->fail(FRBX_E_NOMEM, "device allocation of a table failed");
+    return c->hip(hipMemcpy(dptr, vec.data(), bytes, hipMemcpyHostToDevice), "table upload");
+  };
+  frbx_status s;
+  if ((s = up(c->d_dk, c->dk)) != FRBX_OK) return s;
+  if ((s = up(c->d_rate, rate)) != FRBX_OK) return s;
+  if ((s = up(c->d_tw_sbd, tw_sbd)) != FRBX_OK) return s;
+  if ((s = up(c->d_pre, pre)) != FRBX_OK) return s;
+  if ((s = up(c->d_tw_mbd, tw_mbd)) != FRBX_OK) return s;
+  if ((s = up(c->d_row, c->mbd_row)) != FRBX_OK) return s;
+  if ((s = up(c->d_cal, cal)) != FRBX_OK) return s;
+  c->dirty = false;
+  return FRBX_OK;
+}
+
+template <typename T>
+frbx_status ensure(frbx_ctx *c, T *&p, size_t &cap, size_t need) {
+  if (need <= cap && p) return FRBX_OK;
+  dfree(p);
+  cap = 0;
+  if (need == 0) return FRBX_OK;
+  if (hipMalloc(reinterpret_cast<void **>(&p), need * sizeof(T)) != hipSuccess)
+    return c->fail(FRBX_E_NOMEM, "device allocation failed");
+  cap = need;
+  return FRBX_OK;
+}
+
+// ------------------------------------------------------------ host grouping
+struct Iv {
+  int64_t lo, hi;
+};
+
+// Step b of Sec. 2.4.1: join the lowest-numbered group holding a member whose
+// closed AP interval overlaps; otherwise open a new group.
+int insert_item(std::vector<std::vector<int>> &mem, std::vector<std::vector<Iv>> &ivs, int item,
+                Iv iv) {
+  for (size_t g = 0; g < mem.size(); ++g)
+    for (const Iv &x : ivs[g])
+      if (iv.lo <= x.hi && x.lo <= iv.hi) {
+        mem[g].push_back(item);
+        ivs[g].push_back(iv);
+        return int(g);
+      }
+  mem.push_back({item});
+  ivs.push_back({iv});
+  return int(mem.size()) - 1;
+}
+
+double floor_mod(double a, double p) { return a - p * std::floor(a / p); }
+
+void detect_impl(const frbx_candidate *cr, int64_t nc, double t_amb, int n_win_min, int n_bl_min,
+                 bool use_mbd, std::vector<frbx_candidate> &dets_out,
+                 std::vector<frbx_group> &groups_out) {
+  // per (baseline, DM trial): steps b-d
+  std::vector<int64_t> ord(nc);
+  std::iota(ord.begin(), ord.end(), 0);
+  std::stable_sort(ord.begin(), ord.end(), [&](int64_t x, int64_t y) {
+    if (cr[x].baseline != cr[y].baseline) return cr[x].baseline < cr[y].baseline;
+    return cr[x].dm_index < cr[y].dm_index;
+  });
+  std::vector<std::vector<frbx_candidate>> per_b;
+  std::vector<int> per_b_id;
+  for (int64_t a = 0; a < nc;) {
+    int64_t e = a;
+    while (e < nc && cr[ord[e]].baseline == cr[ord[a]].baseline &&
+           cr[ord[e]].dm_index == cr[ord[a]].dm_index)
+      ++e;
+    std::vector<int64_t> ids(ord.begin() + a, ord.begin() + e);
+    // insertion order: window length descending, then k0, then input order
+    std::vector<int64_t> ins(ids.size());
+    std::iota(ins.begin(), ins.end(), 0);
+    std::stable_sort(ins.begin(), ins.end(), [&](int64_t x, int64_t y) {
+      const frbx_candidate &p = cr[ids[x]], &q = cr[ids[y]];
+      if (p.window_len != q.window_len) return p.window_len > q.window_len;
+      if (p.k0 != q.k0) return p.k0 < q.k0;
+      return ids[x] < ids[y];
+    });
+    std::vector<std::vector<int>> mem;
+    std::vector<std::vector<Iv>> ivs;
+    for (int64_t i : ins) {
+      const frbx_candidate &p = cr[ids[i]];
+      insert_item(mem, ivs, int(i), Iv{p.k0, p.k0 + p.window_len - 1});
+    }
+    const int b = cr[ord[a]].baseline;
+    if (per_b.empty() || per_b_id.back() != b) {
+      per_b.emplace_back();
+      per_b_id.push_back(b);
+    }
+    for (auto &g : mem) {
+      std::vector<int> surv;
+      if (use_mbd) {
+        // step c: circular mean of MBD over the ambiguity, keep |diff| < T/4
+        double sc = 0, ss = 0;
+        for (int i : g) {
+          const double ang = kTwoPi * cr[ids[i]].mbd_us / t_amb;
+          sc += std::cos(ang);
+          ss += std::sin(ang);
+        }
+        const double mbar = t_amb * std::atan2(ss, sc) / kTwoPi;
+        for (int i : g) {
+          const double dlt = floor_mod(cr[ids[i]].mbd_us - mbar + t_amb / 2.0, t_amb) - t_amb / 2.0;
+          if (std::fabs(dlt) < t_amb / 4.0) surv.push_back(i);
+        }
+      } else {
+        surv = g;
+      }
+      if (surv.empty()) continue;
+      std::vector<int> wl;
+      for (int i : surv) wl.push_back(cr[ids[i]].window_len);
+      std::sort(wl.begin(), wl.end());
+      const int n_win = int(std::unique(wl.begin(), wl.end()) - wl.begin());
+      if (n_win < n_win_min) continue;
+      int best = surv[0];
+      for (size_t k = 1; k < surv.size(); ++k)
+        if (cr[ids[surv[k]]].power_norm > cr[ids[best]].power_norm) best = surv[k];
+      frbx_candidate det = cr[ids[best]];
+      det.n_windows = n_win;
+      det.group_id = -1;
+      per_b.back().push_back(det);
+    }
+    a = e;
+  }
+  // best DM bin per pulse (Sec. 5.3), per baseline
+  std::vector<frbx_candidate> dets;
+  for (auto &v : per_b) {
+    std::vector<int> ins(v.size());
+    std::iota(ins.begin(), ins.end(), 0);
+    std::stable_sort(ins.begin(), ins.end(), [&](int x, int y) {
+      if (v[x].dm_index != v[y].dm_index) return v[x].dm_index < v[y].dm_index;
+      if (v[x].k0 != v[y].k0) return v[x].k0 < v[y].k0;
+      return x < y;
+    });
+    std::vector<std::vector<int>> mem;
+    std::vector<std::vector<Iv>> ivs;
+    for (int i : ins) insert_item(mem, ivs, i, Iv{v[i].k0, v[i].k0 + v[i].window_len - 1});
+    for (auto &g : mem) {
+      int best = g[0];
+      for (size_t k = 1; k < g.size(); ++k)
+        if (v[g[k]].power_norm > v[best].power_norm) best = g[k];
+      dets.push_back(v[best]);
+    }
+  }
+  // cross-baseline matching (Sec. 2.4.1)
+  std::vector<int> ins(dets.size());
+  std::iota(ins.begin(), ins.end(), 0);
+  std::stable_sort(ins.begin(), ins.end(), [&](int x, int y) {
+    if (dets[x].baseline != dets[y].baseline) return dets[x].baseline < dets[y].baseline;
+    if (dets[x].k0 != dets[y].k0) return dets[x].k0 < dets[y].k0;
+    return x < y;
+  });
+  std::vector<std::vector<int>> mem;
+  std::vector<std::vector<Iv>> ivs;
+  for (int i : ins) {
+    const int g = insert_item(mem, ivs, i, Iv{dets[i].k0, dets[i].k0 + dets[i].window_len - 1});
+    dets[i].group_id = g;
+  }
+  groups_out.clear();
+  for (size_t g = 0; g < mem.size(); ++g) {
+    std::vector<int> bl;
+    for (int i : mem[g]) bl.push_back(dets[i].baseline);
+    std::sort(bl.begin(), bl.end());
+    frbx_group G{};
+    G.group_id = int(g);
+    G.n_baselines = int(std::unique(bl.begin(), bl.end()) - bl.begin());
+    G.k_start = ivs[g][0].lo;
+    G.k_end = ivs[g][0].hi;
+    for (const Iv &x : ivs[g]) G.k_start = std::min(G.k_start, x.lo), G.k_end = std::max(G.k_end, x.hi);
+    int best = mem[g][0];
+    for (size_t k = 1; k < mem[g].size(); ++k)
+      if (dets[mem[g][k]].power_norm > dets[best].power_norm) best = mem[g][k];
+    G.best = best;
+    G.reported = G.n_baselines >= n_bl_min ? 1 : 0;
+    groups_out.push_back(G);
+  }
+  dets_out.swap(dets);
+}
+
+template <typename T>
+frbx_status copy_out(const std::vector<T> &v, T *out, int64_t cap, int64_t *n) {
+  if (n) *n = int64_t(v.size());
+  if (cap < int64_t(v.size())) return FRBX_E_RANGE;
+  if (out && !v.empty()) std::memcpy(out, v.data(), v.size() * sizeof(T));
+  return FRBX_OK;
+}
+
+}  // namespace
+
+// ================================================================== C ABI
+extern "C" {
+
+const char *frbx_version(void) { return "frbx 0.1 (gfx950)"; }
+
+frbx_status frbx_create(const frbx_layout *L, int device, void *hip_stream, frbx_ctx **out) {
+  if (!out) return FRBX_E_INVAL;
+  *out = nullptr;
+  std::string why;
+  frbx_status s = check_layout(L, why);
+  if (s != FRBX_OK) {
+    std::fprintf(stderr, "frbx_create: %s\n", why.c_str());
+    return s;
+  }
+  int n_dev = 0;
+  if (hipGetDeviceCount(&n_dev) != hipSuccess || device < 0 || device >= n_dev) return FRBX_E_DEVICE;
+  if (hipSetDevice(device) != hipSuccess) return FRBX_E_DEVICE;
+  frbx_ctx *c = new (std::nothrow) frbx_ctx();
+  if (!c) return FRBX_E_NOMEM;
+  c->B = L->n_baselines;
+  c->N = L->n_if;
+  c->J = L->n_chan;
+  c->K = L->n_frames;
+  c->t_ap = L->t_ap_ms;
+  c->df = L->chan_bw_mhz;
+  c->f0.assign(L->if_freq_mhz, L->if_freq_mhz + L->n_if);
+  c->device = device;
+  c->stream = static_cast<hipStream_t>(hip_stream);
+  c->tau0.assign(size_t(c->B) * c->N, 0.0);
+  c->phi0.assign(size_t(c->B) * c->N, 0.0);
+  if (const char *e = std::getenv("FRBX_W_BUDGET_MB")) c->w_budget = size_t(std::atoll(e)) << 20;
+  *out = c;
+  return FRBX_OK;
+}
+
+void frbx_destroy(frbx_ctx *ctx) { delete ctx; }
+
+const char *frbx_last_error(const frbx_ctx *ctx) { return ctx ? ctx->err.c_str() : "null context"; }
+
+frbx_status frbx_set_calibration(frbx_ctx *c, const double *tau0_us, const double *phi0_rad) {
+  if (!c) return FRBX_E_INVAL;
+  const size_t n = size_t(c->B) * c->N;
+  for (size_t i = 0; i < n; ++i) {
+    const double t = tau0_us ? tau0_us[i] : 0.0, p = phi0_rad ? phi0_rad[i] : 0.0;
+    if (!std::isfinite(t) || !std::isfinite(p)) return c->fail(FRBX_E_INVAL, "calibration not finite");
+  }
+  for (size_t i = 0; i < n; ++i) {
+    c->tau0[i] = tau0_us ? tau0_us[i] : 0.0;
+    c->phi0[i] = phi0_rad ? phi0_rad[i] : 0.0;
+  }
+  c->dirty = true;
+  c->have = false;
+  return FRBX_OK;
+}
+
+frbx_status frbx_set_dm_grid(frbx_ctx *c, double dm_lo, double dm_step, int32_t n_dm, double k_dm) {
+  if (!c) return FRBX_E_INVAL;
+  if (n_dm < 1 || n_dm > 65536 || !std::isfinite(dm_lo) || !std::isfinite(dm_step) || dm_lo < 0 ||
+      dm_step < 0 || !std::isfinite(k_dm))
+    return c->fail(FRBX_E_INVAL, "DM grid: need 1 <= n_dm <= 65536 and finite dm_lo, dm_step >= 0");
+  c->dm_lo = dm_lo;
+  c->dm_step = dm_step;
+  c->n_dm = n_dm;
+  c->k_dm = k_dm > 0 ? k_dm : kDefaultKdm;
+  c->dirty = true;
+  c->have = false;
+  return FRBX_OK;
+}
+
+frbx_status frbx_set_delay_grid(frbx_ctx *c, int32_t sbd_pad, int32_t n_mbd, double mbd_step_us,
+                                double f_ref_fit_mhz) {
+  if (!c) return FRBX_E_INVAL;
+  if (!(sbd_pad == 1 || sbd_pad == 2 || sbd_pad == 4 || sbd_pad == 8))
+    return c->fail(FRBX_E_INVAL, "sbd_pad must be 1, 2, 4 or 8");
+  if (!(n_mbd == 16 || n_mbd == 32 || n_mbd == 64 || n_mbd == 128 || n_mbd == 256))
+    return c->fail(FRBX_E_INVAL, "n_mbd must be 16, 32, 64, 128 or 256");
+  if (!std::isfinite(mbd_step_us)) return c->fail(FRBX_E_INVAL, "mbd_step_us not finite");
+  c->sbd_pad = sbd_pad;
+  c->n_mbd = n_mbd;
+  c->mbd_step_req = mbd_step_us;
+  c->f_ref_fit = f_ref_fit_mhz;
+  c->dirty = true;
+  c->have = false;
+  return FRBX_OK;
+}
+
+frbx_status frbx_set_rate_grid(frbx_ctx *c, int32_t n_rate, double rate_step) {
+  if (!c) return FRBX_E_INVAL;
+  if (n_rate < 1 || n_rate > 64 || !std::isfinite(rate_step))
+    return c->fail(FRBX_E_INVAL, "rate grid: need 1 <= n_rate <= 64 and a finite step");
+  c->n_rate = n_rate;
+  c->rate_step_req = rate_step;
+  c->dirty = true;
+  c->have = false;
+  return FRBX_OK;
+}
+
+frbx_status frbx_set_windows(frbx_ctx *c, const int32_t *len, int32_t n) {
+  if (!c) return FRBX_E_INVAL;
+  if (!len || n < 1 || n > frbx::kMaxWindows)
+    return c->fail(FRBX_E_INVAL, "need 1..8 window lengths");
+  std::vector<int> w(len, len + n);
+  for (int i = 0; i < n; ++i) {
+    if (w[i] < 1 || w[i] > 4096) return c->fail(FRBX_E_INVAL, "window length must be 1..4096");
+    for (int k = 0; k < i; ++k)
+      if (w[k] == w[i]) return c->fail(FRBX_E_INVAL, "window lengths must be distinct");
+  }
+  c->windows = w;
+  c->dirty = true;
+  c->have = false;
+  return FRBX_OK;
+}
+
+frbx_status frbx_set_detection(frbx_ctx *c, double threshold, int32_t n_win_min, int32_t n_bl_min) {
+  if (!c) return FRBX_E_INVAL;
+  if (!std::isfinite(threshold) || n_win_min < 1 || n_bl_min < 1)
+    return c->fail(FRBX_E_INVAL, "detection: finite threshold, n_win_min >= 1, n_bl_min >= 1");
+  c->threshold = threshold;
+  c->n_win_min = n_win_min;
+  c->n_bl_min = n_bl_min;
+  c->have = false;
+  return FRBX_OK;
+}
+
+frbx_status frbx_load(frbx_ctx *c, const void *vis, int is_device) {
+  if (!c) return FRBX_E_INVAL;
+  if (!vis) return c->fail(FRBX_E_INVAL, "vis is NULL");
+  if (hipSetDevice(c->device) != hipSuccess) return c->fail(FRBX_E_DEVICE, "hipSetDevice failed");
+  c->have = false;
+  c->loaded = false;
+  const size_t bytes = size_t(c->B) * c->N * c->J * size_t(c->K) * sizeof(float2);
+  if (is_device) {
+    hipPointerAttribute_t at;
+    if (hipPointerGetAttributes(&at, vis) != hipSuccess || at.type != hipMemoryTypeDevice)
+      return c->fail(FRBX_E_INVAL, "vis is not a device pointer");
+    if (at.device != c->device) return c->fail(FRBX_E_INVAL, "vis is on another device");
+    dfree(c->d_vis_own);
+    c->d_vis = static_cast<const float2 *>(vis);
+  } else {
+    dfree(c->d_vis_own);
+    if (hipMalloc(reinterpret_cast<void **>(&c->d_vis_own), bytes) != hipSuccess)
+      return c->fail(FRBX_E_NOMEM, "device allocation for the cross spectra failed");
+    frbx_status s = c->hip(hipMemcpyAsync(c->d_vis_own, vis, bytes, hipMemcpyHostToDevice, c->stream),
+                           "upload of cross spectra");
+    if (s == FRBX_OK) s = c->hip(hipStreamSynchronize(c->stream), "upload of cross spectra");
+    if (s != FRBX_OK) return s;
+    c->d_vis = c->d_vis_own;
+  }
+  c->loaded = true;
+  return FRBX_OK;
+}
+
+frbx_status frbx_run(frbx_ctx *c) {
+  if (!c) return FRBX_E_INVAL;
+  if (!c->loaded) return c->fail(FRBX_E_STATE, "frbx_run before frbx_load");
+  if (hipSetDevice(c->device) != hipSuccess) return c->fail(FRBX_E_DEVICE, "hipSetDevice failed");
+  c->have = false;
+  c->spans.clear();
+  c->ev_used = 0;
+  frbx_status s = prepare(c);
+  if (s != FRBX_OK) return s;
+  const int B = c->B, D = c->n_dm, NJ = c->N * c->J, nw = int(c->windows.size());
+  const int64_t S = c->seg_total;
+  // workspaces
+  const size_t per_dm = size_t(std::max<int64_t>(c->k_eff, 0)) * NJ;
+  c->dt = per_dm ? int(std::max<size_t>(1, std::min<size_t>(D, c->w_budget / (per_dm * sizeof(float2))))) : 1;
+  while (c->dt > 1 && int64_t(c->dt) * S > (int64_t(1) << 31) - 1) c->dt /= 2;
+  if ((s = ensure(c, c->d_w, c->w_cap, per_dm * c->dt)) != FRBX_OK) return s;
+  const size_t cube = size_t(B) * D * S;
+  if ((s = ensure(c, c->d_power, c->cube_cap, cube)) != FRBX_OK) return s;
+  if ((s = ensure(c, c->d_pidx, c->pidx_cap, cube)) != FRBX_OK) return s;
+  const size_t rows = size_t(B) * D * nw;
+  if ((s = ensure(c, c->d_mean, c->mean_cap, rows)) != FRBX_OK) return s;
+  if ((s = ensure(c, c->d_sd, c->sd_cap, rows)) != FRBX_OK) return s;
+  if ((s = ensure(c, c->d_cnt, c->cnt_cap, rows)) != FRBX_OK) return s;
+  if (!c->d_ncross && hipMalloc(reinterpret_cast<void **>(&c->d_ncross), sizeof(unsigned long long)) != hipSuccess)
+    return c->fail(FRBX_E_NOMEM, "device allocation failed");
+  const int64_t want_cap = std::max<int64_t>(int64_t(1) << 16, int64_t(cube / 64));
+  if (c->cross_cap < want_cap) {
+    dfree(c->d_cross);
+    c->cross_cap = 0;
+    if (hipMalloc(reinterpret_cast<void **>(&c->d_cross), size_t(want_cap) * sizeof(DevCrossing)) != hipSuccess)
+      return c->fail(FRBX_E_NOMEM, "device allocation failed");
+    c->cross_cap = want_cap;
+  }
+  const int J = c->J, M = c->n_mbd;
+  const size_t lds = frbx::fringe_lds_bytes(J, M, c->N, c->sbd_pad);
+  if (S > 0 && c->k_eff > 0) {
+    for (int b = 0; b < B; ++b) {
+      for (int d0 = 0; d0 < D; d0 += c->dt) {
+        const int ndt = std::min(c->dt, D - d0);
+        frbx::DedisperseArgs da{};
+        da.vis = c->d_vis + size_t(b) * NJ * size_t(c->K);
+        da.n_frames = c->K;
+        da.dk = c->d_dk;
+        da.d0 = d0;
+        da.n_dt = ndt;
+        da.cal = c->d_cal + size_t(b) * NJ;
+        da.out = c->d_w;
+        da.k_eff = c->k_eff;
+        da.nj = NJ;
+        int sp = c->span_begin(1, int64_t(ndt) * c->k_eff);
+        if ((s = c->hip(frbx::launch_dedisperse(da, c->stream), "dedisperse launch")) != FRBX_OK) return s;
+        c->span_end(sp);
+        frbx::FringeArgs fa{};
+        fa.w = c->d_w;
+        fa.w_dm_stride = c->k_eff * NJ;
+        fa.n_if = c->N;
+        fa.n_rate = c->n_rate;
+        fa.sbd_pad = c->sbd_pad;
+        fa.n_win = nw;
+        for (int w = 0; w < nw; ++w) {
+          fa.win_len[w] = c->windows[w];
+          fa.win_hop[w] = c->hop[w];
+          fa.win_off[w] = c->segoff[w];
+          fa.rate_off[w] = c->rate_off[w];
+        }
+        fa.seg_total = int(S);
+        fa.n_dt = ndt;
+        fa.rate_ph = c->d_rate;
+        fa.tw_sbd = c->d_tw_sbd;
+        fa.pre_sbd = c->d_pre;
+        fa.tw_mbd = c->d_tw_mbd;
+        fa.mbd_row = c->d_row;
+        fa.power = c->d_power + (size_t(b) * D + d0) * S;
+        fa.pidx = c->d_pidx + (size_t(b) * D + d0) * S;
+        fa.dump = nullptr;
+        sp = c->span_begin(0, int64_t(ndt) * S);
+        if ((s = c->hip(frbx::launch_fringe(J, M, fa, lds, int(ndt * S), c->stream), "fringe launch")) != FRBX_OK)
+          return s;
+        c->span_end(sp);
+      }
+    }
+  }
+  // Eq. 6 statistics and threshold crossings
+  frbx::StatsArgs st{};
+  st.power = c->d_power;
+  st.pidx = c->d_pidx;
+  st.seg_total = int(S);
+  st.n_win = nw;
+  for (int w = 0; w < nw; ++w) {
+    st.win_off[w] = c->segoff[w];
+    st.win_q[w] = c->nseg[w];
+  }
+  st.threshold = c->threshold;
+  st.mean = c->d_mean;
+  st.stdev = c->d_sd;
+  st.count = c->d_cnt;
+  st.out = c->d_cross;
+  st.n_out = c->d_ncross;
+  st.cap = c->cross_cap;
+  unsigned long long ncr = 0;
+  for (int attempt = 0; attempt < 2; ++attempt) {
+    if ((s = c->hip(hipMemsetAsync(c->d_ncross, 0, sizeof(unsigned long long), c->stream), "memset")) != FRBX_OK)
+      return s;
+    const int sp = S > 0 ? c->span_begin(2, int64_t(rows)) : -1;
+    if (S > 0 && (s = c->hip(frbx::launch_stats(st, int(rows), c->stream), "stats launch")) != FRBX_OK) return s;
+    c->span_end(sp);
+    if ((s = c->hip(hipMemcpyAsync(&ncr, c->d_ncross, sizeof(ncr), hipMemcpyDeviceToHost, c->stream),
+                    "crossing count")) != FRBX_OK)
+      return s;
+    if ((s = c->hip(hipStreamSynchronize(c->stream), "search")) != FRBX_OK) return s;
+    if (int64_t(ncr) <= c->cross_cap) break;
+    dfree(c->d_cross);
+    c->cross_cap = 0;
+    if (hipMalloc(reinterpret_cast<void **>(&c->d_cross), size_t(ncr) * sizeof(DevCrossing)) != hipSuccess)
+      return c->fail(FRBX_E_NOMEM, "device allocation for crossings failed");
+    c->cross_cap = int64_t(ncr);
+    st.out = c->d_cross;
+    st.cap = c->cross_cap;
+  }
+  if (c->timing) c->collect_timing();
+  std::vector<DevCrossing> hc(ncr);
+  c->mean.assign(rows, 0.0);
+  c->sd.assign(rows, 0.0);
+  c->cnt.assign(rows, 0);
+  if (ncr && (s = c->hip(hipMemcpy(hc.data(), c->d_cross, ncr * sizeof(DevCrossing), hipMemcpyDeviceToHost),
+                         "crossings copy")) != FRBX_OK)
+    return s;
+  if (rows && S > 0) {
+    if ((s = c->hip(hipMemcpy(c->mean.data(), c->d_mean, rows * sizeof(double), hipMemcpyDeviceToHost), "stats")) != FRBX_OK ||
+        (s = c->hip(hipMemcpy(c->sd.data(), c->d_sd, rows * sizeof(double), hipMemcpyDeviceToHost), "stats")) != FRBX_OK ||
+        (s = c->hip(hipMemcpy(c->cnt.data(), c->d_cnt, rows * sizeof(int64_t), hipMemcpyDeviceToHost), "stats")) != FRBX_OK)
+      return s;
+  }
+  std::sort(hc.begin(), hc.end(), [](const DevCrossing &x, const DevCrossing &y) {
+    return x.row != y.row ? x.row < y.row : x.q < y.q;
+  });
+  const int PJ = c->sbd_pad * J;
+  c->cross.clear();
+  c->cross.reserve(hc.size());
+  for (const DevCrossing &x : hc) {
+    frbx_candidate k{};
+    const int w = x.row % nw, bd = x.row / nw;
+    k.baseline = bd / D;
+    k.dm_index = bd % D;
+    k.window_index = w;
+    k.window_len = c->windows[w];
+    k.segment = x.q;
+    k.k0 = int64_t(x.q) * c->hop[w];
+    k.dm = c->dm_lo + k.dm_index * c->dm_step;
+    k.power = x.power;
+    k.power_norm = x.pnorm;
+    const int m = x.idx % M, sb = (x.idx / M) % PJ, r = x.idx / (M * PJ);
+    k.rate_idx = r;
+    k.sbd_idx = sb;
+    k.mbd_idx = m;
+    k.rate = (r - c->n_rate / 2) * c->rate_step;
+    k.sbd_us = (sb - PJ / 2.0) / (PJ * c->df);
+    k.mbd_us = (m - M / 2.0) * c->mbd_step;
+    k.n_windows = 0;
+    k.group_id = -1;
+    c->cross.push_back(k);
+  }
+  detect_impl(c->cross.data(), int64_t(c->cross.size()), c->t_amb, c->n_win_min, c->n_bl_min, true,
+              c->dets, c->groups);
+  c->have = true;
+  return FRBX_OK;
+}
+
+frbx_status frbx_get_segments(const frbx_ctx *cc, int64_t *dk_max, int32_t *hop, int64_t *n_seg,
+                              int64_t *cube_len) {
+  frbx_ctx *c = const_cast<frbx_ctx *>(cc);
+  if (!c) return FRBX_E_INVAL;
+  frbx_status s = prepare(c);
+  if (s != FRBX_OK) return s;
+  if (dk_max) *dk_max = c->dk_max;
+  for (size_t w = 0; w < c->windows.size(); ++w) {
+    if (hop) hop[w] = c->hop[w];
+    if (n_seg) n_seg[w] = c->nseg[w];
+  }
+  if (cube_len) *cube_len = c->seg_total;
+  return FRBX_OK;
+}
+
+frbx_status frbx_get_ap_offsets(const frbx_ctx *cc, int32_t *out, int64_t cap, int64_t *n) {
+  frbx_ctx *c = const_cast<frbx_ctx *>(cc);
+  if (!c) return FRBX_E_INVAL;
+  frbx_status s = prepare(c);
+  if (s != FRBX_OK) return s;
+  return copy_out(c->dk, out, cap, n);
+}
+
+frbx_status frbx_get_power_cube(const frbx_ctx *c, float *power, int32_t *idx, int64_t cap, int64_t *n) {
+  if (!c) return FRBX_E_INVAL;
+  if (!c->have) return FRBX_E_STATE;
+  const int64_t len = int64_t(c->B) * c->n_dm * c->seg_total;
+  if (n) *n = len;
+  if (cap < len) return FRBX_E_RANGE;
+  hipSetDevice(c->device);
+  if (power && len && hipMemcpy(power, c->d_power, len * sizeof(float), hipMemcpyDeviceToHost) != hipSuccess)
+    return FRBX_E_DEVICE;
+  if (idx && len && hipMemcpy(idx, c->d_pidx, len * sizeof(int32_t), hipMemcpyDeviceToHost) != hipSuccess)
+    return FRBX_E_DEVICE;
+  return FRBX_OK;
+}
+
+frbx_status frbx_get_power_cube_device(const frbx_ctx *c, const float **power, const int32_t **idx) {
+  if (!c) return FRBX_E_INVAL;
+  if (!c->have) return FRBX_E_STATE;
+  if (power) *power = c->d_power;
+  if (idx) *idx = c->d_pidx;
+  return FRBX_OK;
+}
+
+frbx_status frbx_get_stats(const frbx_ctx *c, double *mean, double *stdev, int64_t *count, int64_t cap,
+                           int64_t *n) {
+  if (!c) return FRBX_E_INVAL;
+  if (!c->have) return FRBX_E_STATE;
+  const int64_t len = int64_t(c->mean.size());
+  if (n) *n = len;
+  if (cap < len) return FRBX_E_RANGE;
+  if (mean) std::copy(c->mean.begin(), c->mean.end(), mean);
+  if (stdev) std::copy(c->sd.begin(), c->sd.end(), stdev);
+  if (count) std::copy(c->cnt.begin(), c->cnt.end(), count);
+  return FRBX_OK;
+}
+
+frbx_status frbx_get_crossings(const frbx_ctx *c, frbx_candidate *out, int64_t cap, int64_t *n) {
+  if (!c) return FRBX_E_INVAL;
+  if (!c->have) return FRBX_E_STATE;
+  return copy_out(c->cross, out, cap, n);
+}
+
+frbx_status frbx_get_candidates(const frbx_ctx *c, frbx_candidate *out, int64_t cap, int64_t *n) {
+  if (!c) return FRBX_E_INVAL;
+  if (!c->have) return FRBX_E_STATE;
+  return copy_out(c->dets, out, cap, n);
+}
+
+frbx_status frbx_get_groups(const frbx_ctx *c, frbx_group *out, int64_t cap, int64_t *n) {
+  if (!c) return FRBX_E_INVAL;
+  if (!c->have) return FRBX_E_STATE;
+  return copy_out(c->groups, out, cap, n);
+}
+
+frbx_status frbx_dump_segment(frbx_ctx *c, int32_t b, int32_t d, int32_t w, int64_t q, float *dev_out) {
+  if (!c) return FRBX_E_INVAL;
+  if (!c->loaded) return c->fail(FRBX_E_STATE, "dump before frbx_load");
+  if (!dev_out) return c->fail(FRBX_E_INVAL, "dev_out is NULL");
+  if (hipSetDevice(c->device) != hipSuccess) return c->fail(FRBX_E_DEVICE, "hipSetDevice failed");
+  frbx_status s = prepare(c);
+  if (s != FRBX_OK) return s;
+  if (b < 0 || b >= c->B || d < 0 || d >= c->n_dm || w < 0 || w >= int(c->windows.size()) || q < 0 ||
+      q >= c->nseg[w])
+    return c->fail(FRBX_E_INVAL, "segment out of range");
+  const int NJ = c->N * c->J;
+  const size_t per_dm = size_t(c->k_eff) * NJ;
+  if ((s = ensure(c, c->d_w, c->w_cap, std::max(c->w_cap, per_dm))) != FRBX_OK) return s;
+  frbx::DedisperseArgs da{};
+  da.vis = c->d_vis + size_t(b) * NJ * size_t(c->K);
+  da.n_frames = c->K;
+  da.dk = c->d_dk;
+  da.d0 = d;
+  da.n_dt = 1;
+  da.cal = c->d_cal + size_t(b) * NJ;
+  da.out = c->d_w;
+  da.k_eff = c->k_eff;
+  da.nj = NJ;
+  if ((s = c->hip(frbx::launch_dedisperse(da, c->stream), "dedisperse launch")) != FRBX_OK) return s;
+  frbx::FringeArgs fa{};
+  fa.w = c->d_w;
+  fa.w_dm_stride = c->k_eff * NJ;
+  fa.n_if = c->N;
+  fa.n_rate = c->n_rate;
+  fa.sbd_pad = c->sbd_pad;
+  fa.n_win = int(c->windows.size());
+  for (int i = 0; i < fa.n_win; ++i) {
+    fa.win_len[i] = c->windows[i];
+    fa.win_hop[i] = c->hop[i];
+    fa.win_off[i] = c->segoff[i];
+    fa.rate_off[i] = c->rate_off[i];
+  }
+  fa.seg_total = int(c->seg_total);
+  fa.n_dt = 1;
+  fa.rate_ph = c->d_rate;
+  fa.tw_sbd = c->d_tw_sbd;
+  fa.pre_sbd = c->d_pre;
+  fa.tw_mbd = c->d_tw_mbd;
+  fa.mbd_row = c->d_row;
+  fa.dump = dev_out;
+  fa.dump_dl = 0;
+  fa.dump_seg = int(c->segoff[w] + q);
+  const size_t lds = frbx::fringe_lds_bytes(c->J, c->n_mbd, c->N, c->sbd_pad);
+  if ((s = c->hip(frbx::launch_fringe(c->J, c->n_mbd, fa, lds, 1, c->stream), "fringe launch")) != FRBX_OK)
+    return s;
+  return c->hip(hipStreamSynchronize(c->stream), "dump");
+}
+
+frbx_status frbx_set_timing(frbx_ctx *c, int enable) {
+  if (!c) return FRBX_E_INVAL;
+  c->timing = enable != 0;
+  return FRBX_OK;
+}
+
+frbx_status frbx_get_timing(const frbx_ctx *c, frbx_timing *out) {
+  if (!c || !out) return FRBX_E_INVAL;
+  if (!c->have) return FRBX_E_STATE;
+  *out = c->last_timing;
+  return FRBX_OK;
+}
+
+frbx_status frbx_ap_offsets(const frbx_layout *L, double dm_lo, double dm_step, int32_t n_dm, double k_dm,
+                            int32_t *out) {
+  std::string why;
+  if (check_layout(L, why) != FRBX_OK || !out || n_dm < 1 || !std::isfinite(dm_lo) || !std::isfinite(dm_step))
+    return FRBX_E_INVAL;
+  ap_offset_table(L->n_if, L->n_chan, L->if_freq_mhz, L->chan_bw_mhz, L->t_ap_ms, dm_lo, dm_step, n_dm,
+                  k_dm > 0 ? k_dm : kDefaultKdm, out);
+  return FRBX_OK;
+}
+
+frbx_status frbx_detect(const frbx_candidate *crossings, int64_t n_cross, double t_amb_us, int32_t n_win_min,
+                        int32_t n_bl_min, int32_t use_mbd, frbx_candidate *dets, int64_t det_cap,
+                        int64_t *n_dets, frbx_group *groups, int64_t group_cap, int64_t *n_groups) {
+  if (n_cross < 0 || (n_cross > 0 && !crossings) || !(t_amb_us > 0) || n_win_min < 1 || n_bl_min < 1)
+    return FRBX_E_INVAL;
+  std::vector<frbx_candidate> d;
+  std::vector<frbx_group> g;
+  detect_impl(crossings, n_cross, t_amb_us, n_win_min, n_bl_min, use_mbd != 0, d, g);
+  frbx_status s1 = copy_out(d, dets, det_cap, n_dets);
+  frbx_status s2 = copy_out(g, groups, group_cap, n_groups);
+  return s1 != FRBX_OK ? s1 : s2;
+}
+
+}  // extern "C"

@@ -1,0 +1,90 @@
+// Internal interface between the host side of libfrbx and its HIP kernels.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace frbx {
+
+constexpr int kMaxWindows = 8;
+constexpr int kBlock = 256;  // threads per work-group of every kernel
+
+// One threshold crossing as written by the statistics kernel.
+struct DevCrossing {
+  int32_t row;    // (b * D + d) * n_windows + window
+  int32_t q;      // segment index within the window
+  float power;    // |G| peak
+  int32_t idx;    // packed (r * PJ + s) * M + m
+  double pnorm;   // Eq. 6
+};
+
+// Dedispersion of one baseline for a tile of DM trials (Eqs. 1-3): the
+// dedispersed, calibrated AP sequence W[dl][k][c] = cal[c] * V[c][k + dk[d][c]]
+// for k < k_eff and channel c = n * J + j.
+struct DedisperseArgs {
+  const float2 *vis;   // [NJ][K] of this baseline
+  int64_t n_frames;    // K
+  const int32_t *dk;   // [D][NJ]
+  int32_t d0;          // first DM trial of the tile
+  int32_t n_dt;        // DM trials in the tile
+  const float2 *cal;   // [NJ] of this baseline
+  float2 *out;         // [n_dt][k_eff][NJ]
+  int64_t k_eff;       // K - dk_max
+  int32_t nj;          // N * J
+};
+
+// Fringe search of every segment of one baseline and DM tile (Sec. 2.3,
+// Eq. 5 with the rate term of Eq. 4; Sec. 5.1): segment sums of W with rate
+// rotation, zero-padded SBD transform per IF, MBD transform across the IF
+// lattice, and the peak of |G| over (rate, SBD, MBD).
+struct FringeArgs {
+  const float2 *w;           // [n_dt][k_eff][NJ]
+  int64_t w_dm_stride;       // k_eff * NJ
+  int32_t n_if;              // N
+  int32_t n_rate;            // R
+  int32_t sbd_pad;           // P
+  int32_t n_win;
+  int32_t win_len[kMaxWindows];
+  int32_t win_hop[kMaxWindows];
+  int32_t win_off[kMaxWindows];   // first cube segment of the window
+  int32_t rate_off[kMaxWindows];  // offset (float2) of the window's [R][N][l] phasors
+  int32_t seg_total;               // segments per (b, d)
+  int32_t n_dt;                    // DM trials in this launch
+  const float2 *rate_ph;
+  const float2 *tw_sbd;      // [PJ]      exp(-2 pi i k / PJ)
+  const float2 *pre_sbd;     // [P][JA]   exp(-2 pi i i1 c / (P JA))
+  const float2 *tw_mbd;      // [M]       exp(-2 pi i k / M)
+  const int32_t *mbd_row;    // [M]       IF on lattice position q, N if none
+  float *power;              // [n_dt][seg_total] cube rows of (b, d0)
+  int32_t *pidx;
+  float *dump;               // non-null: one segment, |G|^2 of every cell
+  int32_t dump_dl;
+  int32_t dump_seg;
+};
+
+struct StatsArgs {
+  const float *power;        // [B*D][seg_total]
+  const int32_t *pidx;
+  int32_t seg_total;
+  int32_t n_win;
+  int32_t win_off[kMaxWindows];
+  int32_t win_q[kMaxWindows];
+  double threshold;
+  double *mean;              // [B*D*n_win]
+  double *stdev;
+  int64_t *count;
+  DevCrossing *out;
+  unsigned long long *n_out;
+  int64_t cap;
+};
+
+// Launch wrappers (defined in frbx_kernels.hip).  They return the HIP status
+// of the launch.
+hipError_t launch_dedisperse(const DedisperseArgs &a, hipStream_t s);
+hipError_t launch_fringe(int n_chan, int n_mbd, const FringeArgs &a, size_t lds_bytes,
+                         int grid, hipStream_t s);
+size_t fringe_lds_bytes(int n_chan, int n_mbd, int n_if, int sbd_pad);
+bool fringe_supported(int n_chan, int n_mbd, int n_if, int sbd_pad);
+hipError_t launch_stats(const StatsArgs &a, int rows, hipStream_t s);
+
+}  // namespace frbx

@@ -1,0 +1,600 @@
+// HIP kernels of the cross-spectrum FRB search for gfx950 (MI355X).
+//
+//   dedisperse_kernel  Eqs. 1-3 (Sec. 2.2) and the Eq. 5 calibration: shifts
+//                      every channel by its AP offset for each DM trial of a
+//                      tile and transposes to AP-major order, so that the
+//                      segment sums of the fringe kernel read whole spectra.
+//                      HBM-bound; LDS-tiled transpose, coalesced both ways.
+//   fringe_kernel      Eq. 5 with the Eq. 4 rate term, Sec. 5.1: one
+//                      work-group per segment; for each rate bin it forms the
+//                      segment sums in registers, runs the zero-padded SBD
+//                      transform per IF as P sub-DFTs of J points (two
+//                      in-register passes with an LDS transpose), then the
+//                      M-point MBD transform over the IF lattice for each SBD
+//                      column (two in-register passes, wave-local LDS
+//                      transpose) and keeps the peak of |G|^2.  VALU-bound.
+//   stats_kernel       Eq. 6 and the threshold of Sec. 2.4.1 per (baseline,
+//                      DM trial, window): float64 two-pass mean / population
+//                      deviation, ordered compaction of the crossings.
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <cmath>
+#include <type_traits>
+
+#include "frbx_internal.h"
+
+namespace frbx {
+namespace {
+
+// ---------------------------------------------------------------- helpers
+template <int I, int N, typename F>
+__device__ __forceinline__ void static_for(F &&f) {
+  if constexpr (I < N) {
+    f(std::integral_constant<int, I>{});
+    static_for<I + 1, N>(f);
+  }
+}
+
+constexpr int ilog2(int n) { return n <= 1 ? 0 : 1 + ilog2(n >> 1); }
+
+constexpr int bitrev(int i, int bits) {
+  int r = 0;
+  for (int b = 0; b < bits; ++b) r |= ((i >> b) & 1) << (bits - 1 - b);
+  return r;
+}
+
+// Compile-time sine/cosine of (pi/2) * x, x in [0, 1), by Taylor series in
+// double; used only for the fixed twiddles of the in-register DFTs.
+constexpr double kHalfPi = 1.57079632679489661923;
+constexpr double taylor_sin(double t) {
+  double term = t, sum = t;
+  for (int i = 1; i < 18; ++i) {
+    term *= -t * t / ((2.0 * i) * (2.0 * i + 1.0));
+    sum += term;
+  }
+  return sum;
+}
+constexpr double taylor_cos(double t) {
+  double term = 1.0, sum = 1.0;
+  for (int i = 1; i < 18; ++i) {
+    term *= -t * t / ((2.0 * i - 1.0) * (2.0 * i));
+    sum += term;
+  }
+  return sum;
+}
+// exp(-2 pi i k / n) = (c, s): quadrant reduction on the integers first.
+constexpr double tw_re(int k, int n) {
+  k = ((k % n) + n) % n;
+  const int q = (4 * k) / n;
+  const double t = kHalfPi * double(4 * k - q * n) / double(n);
+  const double c = taylor_cos(t), s = taylor_sin(t);
+  return q == 0 ? c : q == 1 ? -s : q == 2 ? -c : s;
+}
+constexpr double tw_im(int k, int n) {
+  k = ((k % n) + n) % n;
+  const int q = (4 * k) / n;
+  const double t = kHalfPi * double(4 * k - q * n) / double(n);
+  const double c = taylor_cos(t), s = taylor_sin(t);
+  const double sn = q == 0 ? s : q == 1 ? c : q == 2 ? -s : -c;  // sin(2 pi k / n)
+  return -sn;
+}
+
+__device__ __forceinline__ float2 cadd(float2 a, float2 b) { return make_float2(a.x + b.x, a.y + b.y); }
+__device__ __forceinline__ float2 csub(float2 a, float2 b) { return make_float2(a.x - b.x, a.y - b.y); }
+__device__ __forceinline__ float2 cmul(float2 a, float2 b) {
+  return make_float2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
+}
+
+// a * exp(-2 pi i K / N) with the twiddle known at compile time.
+template <int K, int N>
+__device__ __forceinline__ float2 twmul(float2 a) {
+  constexpr int k = ((K % N) + N) % N;
+  if constexpr (k == 0) {
+    return a;
+  } else if constexpr (4 * k == N) {
+    return make_float2(a.y, -a.x);
+  } else if constexpr (2 * k == N) {
+    return make_float2(-a.x, -a.y);
+  } else if constexpr (4 * k == 3 * N) {
+    return make_float2(-a.y, a.x);
+  } else {
+    constexpr float c = static_cast<float>(tw_re(k, N));
+    constexpr float s = static_cast<float>(tw_im(k, N));
+    return make_float2(a.x * c - a.y * s, a.x * s + a.y * c);
+  }
+}
+
+// In-register forward DFT of NP points, X[k] = sum_i x[i] exp(-2 pi i ik/NP):
+// radix-2 decimation in frequency, natural order in and out.
+template <int NP>
+__device__ __forceinline__ void dft(float2 (&x)[NP]) {
+  constexpr int L = ilog2(NP);
+  static_for<0, L>([&](auto st) {
+    constexpr int span = NP >> (decltype(st)::value + 1);
+    static_for<0, NP / 2>([&](auto bi) {
+      constexpr int b = decltype(bi)::value;
+      constexpr int grp = b / span, pos = b % span;
+      constexpr int i0 = grp * 2 * span + pos, i1 = i0 + span;
+      const float2 a = x[i0], c = x[i1];
+      x[i0] = cadd(a, c);
+      x[i1] = twmul<pos * (NP / (2 * span)), NP>(csub(a, c));
+    });
+  });
+  float2 y[NP];
+  static_for<0, NP>([&](auto i) {
+    constexpr int ii = decltype(i)::value;
+    y[bitrev(ii, L)] = x[ii];
+  });
+  static_for<0, NP>([&](auto i) { x[decltype(i)::value] = y[decltype(i)::value]; });
+}
+
+// Make the LDS writes of this wave visible to its other lanes before they
+// read, and keep the compiler from moving LDS accesses across the point.
+__device__ __forceinline__ void wave_lds_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// Size split of an F-point transform into (A in-register points of pass 1)
+// x (B lanes of pass 1).
+template <int F> struct Split;
+template <> struct Split<8> { static constexpr int A = 4, B = 2; };
+template <> struct Split<16> { static constexpr int A = 4, B = 4; };
+template <> struct Split<32> { static constexpr int A = 8, B = 4; };
+template <> struct Split<64> { static constexpr int A = 8, B = 8; };
+template <> struct Split<128> { static constexpr int A = 16, B = 8; };
+template <> struct Split<256> { static constexpr int A = 16, B = 16; };
+
+template <int J, int M>
+struct FringeShape {
+  static constexpr int JA = Split<J>::A, JB = Split<J>::B;
+  static constexpr int MA = Split<M>::A, MB = Split<M>::B;
+  static constexpr int G = MA > MB ? MA : MB;    // lanes per MBD column group
+  static constexpr int COLS = kBlock / G;        // columns per round
+  static constexpr int SG = MA * MB + 16;        // float2 per group scratch
+};
+
+// LDS plan (float2 units): X tile [(N+1)][J+1] with row N kept zero, a
+// scratch area shared by the SBD transpose and the MBD transposes, and the
+// PJ-point SBD twiddle table.
+template <int J, int M>
+__host__ __device__ inline void fringe_lds_plan(int n_if, int sbd_pad, int &x_off, int &s_off,
+                                                int &t_off, int &total) {
+  using S = FringeShape<J, M>;
+  const int xs = J + 1;
+  const int x_sz = (n_if + 1) * xs;
+  const int t_sz = n_if * S::JA * (S::JB + 1);
+  const int m_sz = S::COLS * S::SG;
+  const int s_sz = t_sz > m_sz ? t_sz : m_sz;
+  x_off = 0;
+  s_off = x_sz;
+  t_off = x_sz + s_sz;
+  total = t_off + sbd_pad * J;
+}
+
+// ---------------------------------------------------------------- kernels
+__global__ __launch_bounds__(kBlock) void dedisperse_kernel(DedisperseArgs a) {
+  __shared__ float2 tile[64][65];
+  const int64_t kt = int64_t(blockIdx.x) * 64;
+  const int ct = blockIdx.y * 64;
+  const int dl = blockIdx.z;
+  const int32_t *dkd = a.dk + int64_t(a.d0 + dl) * a.nj;
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  for (int i = w; i < 64; i += 4) {
+    const int c = ct + i;
+    const int64_t k = kt + lane;
+    float2 v = make_float2(0.f, 0.f);
+    if (c < a.nj && k < a.k_eff) v = a.vis[int64_t(c) * a.n_frames + k + dkd[c]];
+    tile[i][lane] = v;
+  }
+  __syncthreads();
+  float2 *outd = a.out + int64_t(dl) * a.k_eff * a.nj;
+  const int c = ct + lane;
+  const float2 cal = c < a.nj ? a.cal[c] : make_float2(0.f, 0.f);
+  for (int i = w; i < 64; i += 4) {
+    const int64_t k = kt + i;
+    if (c < a.nj && k < a.k_eff) outd[k * a.nj + c] = cmul(tile[lane][i], cal);
+  }
+}
+
+template <int J, int M>
+__global__ __launch_bounds__(kBlock) void fringe_kernel(FringeArgs a) {
+  using S = FringeShape<J, M>;
+  constexpr int JA = S::JA, JB = S::JB, MA = S::MA, MB = S::MB, G = S::G, COLS = S::COLS;
+  extern __shared__ float2 lds[];
+  __shared__ float red_v[kBlock / 64];
+  __shared__ int32_t red_i[kBlock / 64];
+
+  const int N = a.n_if, R = a.n_rate, P = a.sbd_pad;
+  const int PJ = P * J;
+  const int NJ = N * J;
+  const int t = threadIdx.x;
+
+  // ---- which segment: spread consecutive segments over the 8 XCDs in
+  // contiguous ranges so that overlapping segments share an L2.
+  int dl, seg;
+  if (a.dump) {
+    dl = a.dump_dl;
+    seg = a.dump_seg;
+  } else {
+    // work-groups are dealt to the XCDs round-robin; when the grid splits
+    // evenly, give XCD x the contiguous range [x nb/8, (x+1) nb/8)
+    const int nb = gridDim.x;
+    const int bx = blockIdx.x;
+    const int lb = (nb & 7) == 0 ? (bx & 7) * (nb >> 3) + (bx >> 3) : bx;
+    dl = lb / a.seg_total;
+    seg = lb - dl * a.seg_total;
+  }
+  int wi = 0;
+  while (wi + 1 < a.n_win && a.win_off[wi + 1] <= seg) ++wi;
+  const int l = a.win_len[wi];
+  const int q = seg - a.win_off[wi];
+  const int64_t k0 = int64_t(q) * a.win_hop[wi];
+  const float2 *wd = a.w + int64_t(dl) * a.w_dm_stride + k0 * NJ;
+  const float2 *rph = a.rate_ph + a.rate_off[wi];
+
+  int x_off, s_off, t_off, total;
+  fringe_lds_plan<J, M>(N, P, x_off, s_off, t_off, total);
+  float2 *X = lds + x_off;
+  float2 *Sc = lds + s_off;
+  float2 *TW = lds + t_off;
+  constexpr int XS = J + 1;
+
+  for (int i = t; i < PJ; i += kBlock) TW[i] = a.tw_sbd[i];
+  for (int i = t; i < XS; i += kBlock) X[N * XS + i] = make_float2(0.f, 0.f);
+
+  // ---- per-lane constants of the MBD transform
+  const int grp = t / G, gl = t - grp * G;
+  const bool m_p1 = gl < MB;  // pass-1 lane: lattice residue i2 = gl
+  const bool m_p2 = gl < MA;  // pass-2 lane: output residue k1 = gl
+  float2 twm[MA];
+  int rowoff[MA];
+  if (m_p1) {
+    static_for<0, MA>([&](auto k) {
+      constexpr int kk = decltype(k)::value;
+      twm[kk] = a.tw_mbd[(gl * kk) & (M - 1)];
+      rowoff[kk] = a.mbd_row[MB * kk + gl] * XS;
+    });
+  }
+  float2 *Sg = Sc + grp * S::SG;
+
+  // ---- per-lane roles of the SBD transform
+  const bool s_p1 = t < N * JB;
+  const int n1 = t / JB, i2s = t - (t / JB) * JB;
+
+  float best_v = -1.0f;
+  int32_t best_i = 0x7fffffff;
+
+  for (int r = 0; r < R; ++r) {
+    // segment sum of Eq. 3 with the Eq. 4 rate rotation about the window
+    // centre; channel j = JB * i1 + i2s of IF n1
+    float2 y[JA];
+    static_for<0, JA>([&](auto i) { y[decltype(i)::value] = make_float2(0.f, 0.f); });
+    if (s_p1) {
+      const float2 *src = wd + n1 * J + i2s;
+      const float2 *ph = rph + (r * N + n1) * l;
+      for (int u = 0; u < l; ++u) {
+        if (R > 1) {
+          const float2 p = ph[u];
+          static_for<0, JA>([&](auto i) {
+            constexpr int ii = decltype(i)::value;
+            const float2 v = src[int64_t(u) * NJ + JB * ii];
+            y[ii] = cadd(y[ii], cmul(v, p));
+          });
+        } else {
+          static_for<0, JA>([&](auto i) {
+            constexpr int ii = decltype(i)::value;
+            y[ii] = cadd(y[ii], src[int64_t(u) * NJ + JB * ii]);
+          });
+        }
+      }
+      if (i2s == 0) y[0] = make_float2(0.f, 0.f);  // j = 0 takes no part (Sec. 2.3)
+    }
+
+    for (int c = 0; c < P; ++c) {
+      __syncthreads();
+      // SBD pass 1: x[i1] = y[i1] w_{P JA}^{i1 c}; JA-point DFT over i1;
+      // twiddle w_PJ^{i2 (c + P k1)}; store transposed T[n][k1][i2].
+      if (s_p1) {
+        float2 x[JA];
+        static_for<0, JA>([&](auto i) {
+          constexpr int ii = decltype(i)::value;
+          x[ii] = cmul(y[ii], a.pre_sbd[c * JA + ii]);
+        });
+        dft<JA>(x);
+        static_for<0, JA>([&](auto k) {
+          constexpr int kk = decltype(k)::value;
+          const float2 w = TW[(i2s * (c + P * kk)) & (PJ - 1)];
+          Sc[(n1 * JA + kk) * (JB + 1) + i2s] = cmul(x[kk], w);
+        });
+      }
+      __syncthreads();
+      // SBD pass 2: JB-point DFT over i2 -> X[n][a = k1 + JA k2], the SBD
+      // bin s' = c + P a of the standard (unshifted) transform.
+      for (int v = t; v < N * JA; v += kBlock) {
+        const int n2 = v / JA, k1 = v - (v / JA) * JA;
+        float2 z[JB];
+        static_for<0, JB>([&](auto i) {
+          constexpr int ii = decltype(i)::value;
+          z[ii] = Sc[(n2 * JA + k1) * (JB + 1) + ii];
+        });
+        dft<JB>(z);
+        static_for<0, JB>([&](auto k) {
+          constexpr int kk = decltype(k)::value;
+          X[n2 * XS + k1 + JA * kk] = z[kk];
+        });
+      }
+      __syncthreads();
+
+      // MBD over the IF lattice, one column a of this SBD tile per group.
+      for (int a0 = 0; a0 < J; a0 += COLS) {
+        const int col = a0 + grp;
+        if (col < J) {
+          if (m_p1) {
+            float2 x[MA];
+            static_for<0, MA>([&](auto i) {
+              constexpr int ii = decltype(i)::value;
+              x[ii] = X[rowoff[ii] + col];
+            });
+            dft<MA>(x);
+            static_for<0, MA>([&](auto k) {
+              constexpr int kk = decltype(k)::value;
+              Sg[kk * MB + (gl ^ (kk & (MB - 1)))] = cmul(x[kk], twm[kk]);
+            });
+          }
+          wave_lds_sync();
+          if (m_p2) {
+            float2 z[MB];
+            static_for<0, MB>([&](auto i) {
+              constexpr int ii = decltype(i)::value;
+              z[ii] = Sg[gl * MB + (ii ^ (gl & (MB - 1)))];
+            });
+            dft<MB>(z);
+            // shifted bins: s = (s' + PJ/2) mod PJ, m = gl + MA ((k2 + MB/2) mod MB)
+            const int sp = c + P * col;
+            const int s = (sp + (PJ >> 1)) & (PJ - 1);
+            const int32_t base = (r * PJ + s) * M + gl;
+            float cv = -1.0f;
+            int ck = 0;
+            static_for<0, MB>([&](auto kk) {
+              constexpr int kx = decltype(kk)::value;
+              constexpr int k2 = (kx + MB / 2) & (MB - 1);
+              const float v = z[k2].x * z[k2].x + z[k2].y * z[k2].y;
+              if (v > cv) {
+                cv = v;
+                ck = kx;
+              }
+              if (a.dump) a.dump[base + MA * kx] = v;
+            });
+            const int32_t ci = base + MA * ck;
+            if (cv > best_v || (cv == best_v && ci < best_i)) {
+              best_v = cv;
+              best_i = ci;
+            }
+          }
+          wave_lds_sync();
+        }
+      }
+    }
+  }
+
+  // ---- block reduction: larger |G|^2 wins, ties -> lower packed index
+  for (int off = 32; off > 0; off >>= 1) {
+    const float ov = __shfl_xor(best_v, off, 64);
+    const int32_t oi = __shfl_xor(best_i, off, 64);
+    if (ov > best_v || (ov == best_v && oi < best_i)) {
+      best_v = ov;
+      best_i = oi;
+    }
+  }
+  if ((t & 63) == 0) {
+    red_v[t >> 6] = best_v;
+    red_i[t >> 6] = best_i;
+  }
+  __syncthreads();
+  if (t == 0 && !a.dump) {
+    float bv = red_v[0];
+    int32_t bi = red_i[0];
+    for (int w = 1; w < kBlock / 64; ++w) {
+      if (red_v[w] > bv || (red_v[w] == bv && red_i[w] < bi)) {
+        bv = red_v[w];
+        bi = red_i[w];
+      }
+    }
+    const int64_t o = int64_t(dl) * a.seg_total + seg;
+    a.power[o] = bv >= 0.0f ? sqrtf(bv) : __builtin_nanf("");
+    a.pidx[o] = bv >= 0.0f ? bi : -1;
+  }
+}
+
+// Block-wide sum of a double (all threads get the result).
+__device__ double block_sum(double v, double *sh) {
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+  __syncthreads();
+  if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = v;
+  __syncthreads();
+  double s = 0.0;
+  for (int w = 0; w < kBlock / 64; ++w) s += sh[w];
+  return s;
+}
+
+__global__ __launch_bounds__(kBlock) void stats_kernel(StatsArgs a) {
+  __shared__ double sh[kBlock / 64];
+  __shared__ int wcount[kBlock / 64];
+  __shared__ long long base_sh;
+  const int row = blockIdx.x;
+  const int wi = row % a.n_win;
+  const int bd = row / a.n_win;
+  const int Q = a.win_q[wi];
+  const float *p = a.power + int64_t(bd) * a.seg_total + a.win_off[wi];
+  const int32_t *pi = a.pidx + int64_t(bd) * a.seg_total + a.win_off[wi];
+  double s = 0.0, cnt = 0.0;
+  for (int q = threadIdx.x; q < Q; q += kBlock) {
+    const float v = p[q];
+    if (isfinite(v)) {
+      s += v;
+      cnt += 1.0;
+    }
+  }
+  const double S = block_sum(s, sh);
+  const double C = block_sum(cnt, sh);
+  const double mu = C > 0 ? S / C : 0.0;
+  double s2 = 0.0;
+  for (int q = threadIdx.x; q < Q; q += kBlock) {
+    const float v = p[q];
+    if (isfinite(v)) {
+      const double d = double(v) - mu;
+      s2 += d * d;
+    }
+  }
+  const double S2 = block_sum(s2, sh);
+  const double sd = C > 0 ? sqrt(S2 / C) : 0.0;
+  if (threadIdx.x == 0) {
+    a.mean[row] = mu;
+    a.stdev[row] = sd;
+    a.count[row] = static_cast<int64_t>(C);
+  }
+  if (!(sd > 0.0)) return;
+  // count, reserve, then write the crossings in q order
+  int n_cross = 0;
+  for (int q = threadIdx.x; q < Q; q += kBlock) {
+    const float v = p[q];
+    n_cross += (isfinite(v) && (double(v) - mu) / sd > a.threshold) ? 1 : 0;
+  }
+  const double tot = block_sum(double(n_cross), sh);
+  if (tot == 0.0) return;
+  if (threadIdx.x == 0) base_sh = (long long)atomicAdd(a.n_out, (unsigned long long)tot);
+  __syncthreads();
+  long long pos = base_sh;
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  for (int q0 = 0; q0 < Q; q0 += kBlock) {
+    const int q = q0 + threadIdx.x;
+    bool f = false;
+    double pn = 0.0;
+    if (q < Q) {
+      const float v = p[q];
+      pn = (double(v) - mu) / sd;
+      f = isfinite(v) && pn > a.threshold;
+    }
+    const unsigned long long bal = __ballot(f);
+    const int before = __popcll(bal & ((1ull << lane) - 1ull));
+    if (lane == 0) wcount[wv] = __popcll(bal);
+    __syncthreads();
+    int woff = 0, all = 0;
+    for (int w = 0; w < kBlock / 64; ++w) {
+      if (w < wv) woff += wcount[w];
+      all += wcount[w];
+    }
+    if (f) {
+      const long long o = pos + woff + before;
+      if (o < a.cap) {
+        DevCrossing cr;
+        cr.row = row;
+        cr.q = q;
+        cr.power = p[q];
+        cr.idx = pi[q];
+        cr.pnorm = pn;
+        a.out[o] = cr;
+      }
+    }
+    pos += all;
+    __syncthreads();
+  }
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------- launchers
+hipError_t launch_dedisperse(const DedisperseArgs &a, hipStream_t s) {
+  dim3 grid(unsigned((a.k_eff + 63) / 64), unsigned((a.nj + 63) / 64), unsigned(a.n_dt));
+  hipLaunchKernelGGL(dedisperse_kernel, grid, dim3(kBlock), 0, s, a);
+  return hipGetLastError();
+}
+
+template <int J, int M>
+static hipError_t launch_fringe_t(const FringeArgs &a, size_t lds, int grid, hipStream_t s) {
+  static bool attr_set = false;
+  if (!attr_set) {
+    hipFuncSetAttribute(reinterpret_cast<const void *>(&fringe_kernel<J, M>),
+                        hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
+    attr_set = true;
+  }
+  hipLaunchKernelGGL((fringe_kernel<J, M>), dim3(grid), dim3(kBlock), lds, s, a);
+  return hipGetLastError();
+}
+
+#define FRBX_FOR_M(J)                                              \
+  switch (n_mbd) {                                                 \
+    case 16: return fn.template operator()<J, 16>();               \
+    case 32: return fn.template operator()<J, 32>();               \
+    case 64: return fn.template operator()<J, 64>();               \
+    case 128: return fn.template operator()<J, 128>();             \
+    case 256: return fn.template operator()<J, 256>();             \
+    default: return fn.fail();                                     \
+  }
+
+template <typename Fn>
+static auto dispatch(int n_chan, int n_mbd, Fn &&fn) {
+  switch (n_chan) {
+    case 8: FRBX_FOR_M(8)
+    case 16: FRBX_FOR_M(16)
+    case 32: FRBX_FOR_M(32)
+    case 64: FRBX_FOR_M(64)
+    case 128: FRBX_FOR_M(128)
+    case 256: FRBX_FOR_M(256)
+    default: return fn.fail();
+  }
+}
+
+struct LaunchFn {
+  const FringeArgs &a;
+  size_t lds;
+  int grid;
+  hipStream_t s;
+  template <int J, int M> hipError_t operator()() { return launch_fringe_t<J, M>(a, lds, grid, s); }
+  hipError_t fail() { return hipErrorInvalidValue; }
+};
+
+struct LdsFn {
+  int n_if, sbd_pad;
+  template <int J, int M> size_t operator()() {
+    int xo, so, to, tot;
+    fringe_lds_plan<J, M>(n_if, sbd_pad, xo, so, to, tot);
+    return size_t(tot) * sizeof(float2);
+  }
+  size_t fail() { return 0; }
+};
+
+struct SupportFn {
+  int n_if, sbd_pad;
+  template <int J, int M> bool operator()() {
+    using S = FringeShape<J, M>;
+    int xo, so, to, tot;
+    fringe_lds_plan<J, M>(n_if, sbd_pad, xo, so, to, tot);
+    return n_if * S::JB <= kBlock && size_t(tot) * sizeof(float2) <= 150 * 1024;
+  }
+  bool fail() { return false; }
+};
+
+hipError_t launch_fringe(int n_chan, int n_mbd, const FringeArgs &a, size_t lds_bytes, int grid,
+                         hipStream_t s) {
+  return dispatch(n_chan, n_mbd, LaunchFn{a, lds_bytes, grid, s});
+}
+
+size_t fringe_lds_bytes(int n_chan, int n_mbd, int n_if, int sbd_pad) {
+  return dispatch(n_chan, n_mbd, LdsFn{n_if, sbd_pad});
+}
+
+bool fringe_supported(int n_chan, int n_mbd, int n_if, int sbd_pad) {
+  return dispatch(n_chan, n_mbd, SupportFn{n_if, sbd_pad});
+}
+
+hipError_t launch_stats(const StatsArgs &a, int rows, hipStream_t s) {
+  if (rows <= 0) return hipSuccess;
+  hipLaunchKernelGGL(stats_kernel, dim3(rows), dim3(kBlock), 0, s, a);
+  return hipGetLastError();
+}
+
+}  // namespace frbx

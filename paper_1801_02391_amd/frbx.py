@@ -1,0 +1,331 @@
+"""ctypes binding of libfrbx.so (C ABI declared in include/frbx.h).
+
+Argument marshalling only: every step of the search runs inside the
+library.  PyTorch supplies device memory and the HIP stream.  The library
+must have been built (``python -m paper_1801_02391_amd.build``); loading
+raises if it is missing -- there is no fallback path.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+_LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libfrbx.so")
+_lib = None
+
+OK, E_INVAL, E_STATE, E_RANGE, E_NOMEM, E_DEVICE = range(6)
+_STATUS = {0: "OK", 1: "E_INVAL", 2: "E_STATE", 3: "E_RANGE", 4: "E_NOMEM", 5: "E_DEVICE"}
+
+
+class FrbxError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__(f"{_STATUS.get(status, status)}: {msg}")
+        self.status = status
+
+
+class Layout(C.Structure):
+    _fields_ = [("n_baselines", C.c_int32), ("n_if", C.c_int32), ("n_chan", C.c_int32),
+                ("n_frames", C.c_int64), ("t_ap_ms", C.c_double), ("chan_bw_mhz", C.c_double),
+                ("if_freq_mhz", C.POINTER(C.c_double))]
+
+
+class Candidate(C.Structure):
+    _fields_ = [("baseline", C.c_int32), ("dm_index", C.c_int32), ("window_index", C.c_int32),
+                ("window_len", C.c_int32), ("segment", C.c_int64), ("k0", C.c_int64),
+                ("dm", C.c_double), ("power", C.c_double), ("power_norm", C.c_double),
+                ("rate_idx", C.c_int32), ("sbd_idx", C.c_int32), ("mbd_idx", C.c_int32),
+                ("n_windows", C.c_int32), ("rate", C.c_double), ("sbd_us", C.c_double),
+                ("mbd_us", C.c_double), ("group_id", C.c_int32), ("reserved", C.c_int32)]
+
+
+class Group(C.Structure):
+    _fields_ = [("group_id", C.c_int32), ("n_baselines", C.c_int32), ("k_start", C.c_int64),
+                ("k_end", C.c_int64), ("best", C.c_int32), ("reported", C.c_int32)]
+
+
+class Timing(C.Structure):
+    _fields_ = [("fringe_ms", C.c_double), ("n_fringe", C.c_int64), ("fringe_units", C.c_int64),
+                ("dedisperse_ms", C.c_double), ("n_dedisperse", C.c_int64),
+                ("dedisperse_units", C.c_int64), ("stats_ms", C.c_double), ("n_stats", C.c_int64)]
+
+
+CANDIDATE_FIELDS = [f for f, _ in Candidate._fields_ if f != "reserved"]
+
+_P = C.c_void_p
+_SIGS = {
+    "frbx_version": ([], C.c_char_p),
+    "frbx_create": ([C.POINTER(Layout), C.c_int, _P, C.POINTER(_P)], C.c_int),
+    "frbx_destroy": ([_P], None),
+    "frbx_last_error": ([_P], C.c_char_p),
+    "frbx_set_calibration": ([_P, _P, _P], C.c_int),
+    "frbx_set_dm_grid": ([_P, C.c_double, C.c_double, C.c_int32, C.c_double], C.c_int),
+    "frbx_set_delay_grid": ([_P, C.c_int32, C.c_int32, C.c_double, C.c_double], C.c_int),
+    "frbx_set_rate_grid": ([_P, C.c_int32, C.c_double], C.c_int),
+    "frbx_set_windows": ([_P, _P, C.c_int32], C.c_int),
+    "frbx_set_detection": ([_P, C.c_double, C.c_int32, C.c_int32], C.c_int),
+    "frbx_load": ([_P, _P, C.c_int], C.c_int),
+    "frbx_run": ([_P], C.c_int),
+    "frbx_get_segments": ([_P, _P, _P, _P, _P], C.c_int),
+    "frbx_get_ap_offsets": ([_P, _P, C.c_int64, _P], C.c_int),
+    "frbx_get_power_cube": ([_P, _P, _P, C.c_int64, _P], C.c_int),
+    "frbx_get_power_cube_device": ([_P, _P, _P], C.c_int),
+    "frbx_get_stats": ([_P, _P, _P, _P, C.c_int64, _P], C.c_int),
+    "frbx_get_crossings": ([_P, _P, C.c_int64, _P], C.c_int),
+    "frbx_get_candidates": ([_P, _P, C.c_int64, _P], C.c_int),
+    "frbx_get_groups": ([_P, _P, C.c_int64, _P], C.c_int),
+    "frbx_dump_segment": ([_P, C.c_int32, C.c_int32, C.c_int32, C.c_int64, _P], C.c_int),
+    "frbx_set_timing": ([_P, C.c_int], C.c_int),
+    "frbx_get_timing": ([_P, _P], C.c_int),
+    "frbx_ap_offsets": ([C.POINTER(Layout), C.c_double, C.c_double, C.c_int32, C.c_double, _P],
+                        C.c_int),
+    "frbx_detect": ([_P, C.c_int64, C.c_double, C.c_int32, C.c_int32, C.c_int32, _P, C.c_int64,
+                     _P, _P, C.c_int64, _P], C.c_int),
+}
+
+
+def exported_names():
+    return list(_SIGS)
+
+
+def lib():
+    """Load libfrbx.so (raises if it has not been built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_LIB_PATH):
+            raise FrbxError(E_STATE, f"{_LIB_PATH} is missing: build it with "
+                                     "`python -m paper_1801_02391_amd.build`")
+        L = C.CDLL(_LIB_PATH)
+        for name, (args, res) in _SIGS.items():
+            fn = getattr(L, name)
+            fn.argtypes = args
+            fn.restype = res
+        _lib = L
+    return _lib
+
+
+def version():
+    return lib().frbx_version().decode()
+
+
+def _ptr(a):
+    return None if a is None else a.ctypes.data_as(_P)
+
+
+def _layout_struct(layout):
+    f0 = np.ascontiguousarray(layout["if_freq_mhz"], dtype=np.float64)
+    st = Layout(int(layout["n_baselines"]), len(f0), int(layout["n_chan"]), int(layout["n_frames"]),
+                float(layout["t_ap_ms"]), float(layout["chan_bw_mhz"]),
+                f0.ctypes.data_as(C.POINTER(C.c_double)))
+    return st, f0
+
+
+def records_to_dicts(arr):
+    return [{f: (getattr(r, f)) for f in CANDIDATE_FIELDS} for r in arr]
+
+
+def ap_offsets(layout, dm_lo, dm_step, n_dm, k_dm=0.0):
+    """Host-only Eq. 2 table [D][N][J] from the library (no device needed)."""
+    st, f0 = _layout_struct(layout)
+    out = np.zeros((n_dm, len(f0), int(layout["n_chan"])), dtype=np.int32)
+    s = lib().frbx_ap_offsets(C.byref(st), dm_lo, dm_step, n_dm, k_dm, _ptr(out))
+    if s != OK:
+        raise FrbxError(s, "frbx_ap_offsets")
+    return out
+
+
+def detect(crossings, t_amb_us, n_win_min, n_bl_min, use_mbd=True):
+    """Host-only grouping (steps b-d, best DM, cross matching) over a list of
+    crossing dicts with at least baseline, dm_index, window_len, k0,
+    power_norm, mbd_us.  Returns (detections, groups) as lists of dicts."""
+    arr = (Candidate * max(1, len(crossings)))()
+    for i, c in enumerate(crossings):
+        for f in CANDIDATE_FIELDS:
+            if f in c:
+                setattr(arr[i], f, c[f])
+        if "group_id" not in c:
+            arr[i].group_id = -1
+    nd, ng = C.c_int64(0), C.c_int64(0)
+    L = lib()
+    s = L.frbx_detect(arr, len(crossings), t_amb_us, n_win_min, n_bl_min, int(bool(use_mbd)),
+                      None, 0, C.byref(nd), None, 0, C.byref(ng))
+    if s not in (OK, E_RANGE):
+        raise FrbxError(s, "frbx_detect")
+    dets = (Candidate * max(1, nd.value))()
+    grps = (Group * max(1, ng.value))()
+    s = L.frbx_detect(arr, len(crossings), t_amb_us, n_win_min, n_bl_min, int(bool(use_mbd)),
+                      dets, nd.value, C.byref(nd), grps, ng.value, C.byref(ng))
+    if s != OK:
+        raise FrbxError(s, "frbx_detect")
+    groups = [{f: getattr(grps[i], f) for f, _ in Group._fields_} for i in range(ng.value)]
+    return records_to_dicts(dets[:nd.value]), groups
+
+
+class Search:
+    """One search context on one GPU and one HIP stream."""
+
+    def __init__(self, layout, device=0, stream=None):
+        import torch  # device memory and streams
+        self._torch = torch
+        L = lib()
+        st, self._f0 = _layout_struct(layout)
+        self.layout = dict(layout)
+        if stream is None:
+            stream = torch.cuda.current_stream(device)
+        self.stream = stream
+        h = _P()
+        s = L.frbx_create(C.byref(st), int(device), _P(stream.cuda_stream), C.byref(h))
+        if s != OK:
+            raise FrbxError(s, "frbx_create")
+        self._h = h
+        self.device = device
+        self._vis = None
+        self._windows = [2, 4]
+
+    def close(self):
+        if getattr(self, "_h", None):
+            lib().frbx_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _chk(self, s, what):
+        if s != OK:
+            msg = lib().frbx_last_error(self._h).decode()
+            raise FrbxError(s, f"{what}: {msg}")
+
+    # --------------------------------------------------------------- setup
+    def configure(self, search, tau0_us=None, phi0_rad=None):
+        """Apply a search-parameter dict (keys of the workload 'search'
+        section) and optional calibration [B][N]."""
+        L = lib()
+        h = self._h
+        self._chk(L.frbx_set_dm_grid(h, search["dm_lo"], search["dm_step"], search["n_dm"],
+                                     search.get("k_dm", 0.0)), "set_dm_grid")
+        f_ref = search.get("f_ref_fit_mhz", float("nan"))
+        self._chk(L.frbx_set_delay_grid(h, search["sbd_pad"], search["n_mbd"],
+                                        search.get("mbd_step_us", 0.0), f_ref), "set_delay_grid")
+        self._chk(L.frbx_set_rate_grid(h, search["n_rate"], search.get("rate_step", 0.0)),
+                  "set_rate_grid")
+        w = np.ascontiguousarray(search["windows"], dtype=np.int32)
+        self._windows = list(map(int, w))
+        self._chk(L.frbx_set_windows(h, _ptr(w), len(w)), "set_windows")
+        self._chk(L.frbx_set_detection(h, search["threshold"], search["n_win_min"],
+                                       search["n_bl_min"]), "set_detection")
+        if tau0_us is not None or phi0_rad is not None:
+            t = None if tau0_us is None else np.ascontiguousarray(tau0_us, dtype=np.float64)
+            p = None if phi0_rad is None else np.ascontiguousarray(phi0_rad, dtype=np.float64)
+            self._chk(L.frbx_set_calibration(h, _ptr(t), _ptr(p)), "set_calibration")
+        self.search = dict(search)
+
+    def load(self, vis):
+        """vis: complex64 [B][N][J][K] as a torch tensor (on this device: borrowed)
+        or a numpy array (copied)."""
+        torch = self._torch
+        if isinstance(vis, torch.Tensor):
+            if vis.dtype != torch.complex64 or not vis.is_contiguous():
+                raise FrbxError(E_INVAL, "vis must be a contiguous complex64 tensor")
+            if vis.device.type != "cuda":
+                raise FrbxError(E_INVAL, "vis tensor must live on the GPU")
+            self._vis = vis
+            self._chk(lib().frbx_load(self._h, _P(vis.data_ptr()), 1), "load")
+        else:
+            a = np.ascontiguousarray(vis, dtype=np.complex64)
+            self._chk(lib().frbx_load(self._h, _ptr(a), 0), "load")
+
+    def run(self):
+        self._chk(lib().frbx_run(self._h), "run")
+
+    # ------------------------------------------------------------- results
+    def segments(self):
+        nw = len(self._windows)
+        dkm = C.c_int64(0)
+        hop = np.zeros(nw, dtype=np.int32)
+        nseg = np.zeros(nw, dtype=np.int64)
+        tot = C.c_int64(0)
+        self._chk(lib().frbx_get_segments(self._h, C.byref(dkm), _ptr(hop), _ptr(nseg),
+                                          C.byref(tot)), "get_segments")
+        return dict(dk_max=dkm.value, hop=hop.tolist(), n_seg=nseg.tolist(), total=tot.value)
+
+    def ap_offsets(self):
+        n = C.c_int64(0)
+        L = lib()
+        L.frbx_get_ap_offsets(self._h, None, 0, C.byref(n))
+        out = np.zeros(n.value, dtype=np.int32)
+        self._chk(L.frbx_get_ap_offsets(self._h, _ptr(out), n.value, C.byref(n)), "get_ap_offsets")
+        return out.reshape(self.search["n_dm"], self.layout["n_if"] if "n_if" in self.layout
+                           else len(self._f0), self.layout["n_chan"])
+
+    def power_cube(self):
+        """(power [B][D][S] float32, packed index [B][D][S] int32) on the host."""
+        n = C.c_int64(0)
+        L = lib()
+        s = L.frbx_get_power_cube(self._h, None, None, 0, C.byref(n))
+        if s not in (OK, E_RANGE):
+            self._chk(s, "get_power_cube")
+        p = np.zeros(n.value, dtype=np.float32)
+        i = np.zeros(n.value, dtype=np.int32)
+        self._chk(L.frbx_get_power_cube(self._h, _ptr(p), _ptr(i), n.value, C.byref(n)),
+                  "get_power_cube")
+        B, D = self.layout["n_baselines"], self.search["n_dm"]
+        return p.reshape(B, D, -1), i.reshape(B, D, -1)
+
+    def stats(self):
+        n = C.c_int64(0)
+        L = lib()
+        L.frbx_get_stats(self._h, None, None, None, 0, C.byref(n))
+        m = np.zeros(n.value)
+        s = np.zeros(n.value)
+        c = np.zeros(n.value, dtype=np.int64)
+        self._chk(L.frbx_get_stats(self._h, _ptr(m), _ptr(s), _ptr(c), n.value, C.byref(n)),
+                  "get_stats")
+        return m, s, c
+
+    def _records(self, fn, what):
+        n = C.c_int64(0)
+        s = fn(self._h, None, 0, C.byref(n))
+        if s not in (OK, E_RANGE):
+            self._chk(s, what)
+        arr = (Candidate * max(1, n.value))()
+        self._chk(fn(self._h, arr, n.value, C.byref(n)), what)
+        return records_to_dicts(arr[:n.value])
+
+    def crossings(self):
+        return self._records(lib().frbx_get_crossings, "get_crossings")
+
+    def candidates(self):
+        return self._records(lib().frbx_get_candidates, "get_candidates")
+
+    def groups(self):
+        L = lib()
+        n = C.c_int64(0)
+        s = L.frbx_get_groups(self._h, None, 0, C.byref(n))
+        if s not in (OK, E_RANGE):
+            self._chk(s, "get_groups")
+        arr = (Group * max(1, n.value))()
+        self._chk(L.frbx_get_groups(self._h, arr, n.value, C.byref(n)), "get_groups")
+        return [{f: getattr(arr[i], f) for f, _ in Group._fields_} for i in range(n.value)]
+
+    def set_timing(self, enable=True):
+        self._chk(lib().frbx_set_timing(self._h, int(bool(enable))), "set_timing")
+
+    def timing(self):
+        t = Timing()
+        self._chk(lib().frbx_get_timing(self._h, C.byref(t)), "get_timing")
+        return {f: getattr(t, f) for f, _ in Timing._fields_}
+
+    def dump_segment(self, b, d, wi, q):
+        """|G|^2 of every (rate, SBD, MBD) cell of one segment -> numpy [R][PJ][M]."""
+        torch = self._torch
+        R = self.search["n_rate"]
+        PJ = self.search["sbd_pad"] * self.layout["n_chan"]
+        M = self.search["n_mbd"]
+        out = torch.empty(R * PJ * M, dtype=torch.float32, device=f"cuda:{self.device}")
+        self._chk(lib().frbx_dump_segment(self._h, b, d, wi, q, _P(out.data_ptr())),
+                  "dump_segment")
+        return out.cpu().numpy().reshape(R, PJ, M)
