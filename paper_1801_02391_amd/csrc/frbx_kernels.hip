@@ -508,6 +508,7 @@ __global__ __launch_bounds__(kBlock) void stats_kernel(StatsArgs a) {
 
 // ---------------------------------------------------------------- launchers
 hipError_t launch_dedisperse(const DedisperseArgs &a, hipStream_t s) {
+  (void)hipGetLastError();
   dim3 grid(unsigned((a.k_eff + 63) / 64), unsigned((a.nj + 63) / 64), unsigned(a.n_dt));
   hipLaunchKernelGGL(dedisperse_kernel, grid, dim3(kBlock), 0, s, a);
   return hipGetLastError();
@@ -515,11 +516,11 @@ hipError_t launch_dedisperse(const DedisperseArgs &a, hipStream_t s) {
 
 template <int J, int M>
 static hipError_t launch_fringe_t(const FringeArgs &a, size_t lds, int grid, hipStream_t s) {
-  static bool attr_set = false;
-  if (!attr_set) {
-    hipFuncSetAttribute(reinterpret_cast<const void *>(&fringe_kernel<J, M>),
-                        hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
-    attr_set = true;
+  (void)hipGetLastError();  // start from a clean error state
+  if (lds > 64 * 1024) {
+    const hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(&fringe_kernel<J, M>),
+                                             hipFuncAttributeMaxDynamicSharedMemorySize, int(lds));
+    if (e != hipSuccess) return e;
   }
   hipLaunchKernelGGL((fringe_kernel<J, M>), dim3(grid), dim3(kBlock), lds, s, a);
   return hipGetLastError();
@@ -593,6 +594,7 @@ bool fringe_supported(int n_chan, int n_mbd, int n_if, int sbd_pad) {
 
 hipError_t launch_stats(const StatsArgs &a, int rows, hipStream_t s) {
   if (rows <= 0) return hipSuccess;
+  (void)hipGetLastError();
   hipLaunchKernelGGL(stats_kernel, dim3(rows), dim3(kBlock), 0, s, a);
   return hipGetLastError();
 }
