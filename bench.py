@@ -81,6 +81,9 @@ def main():
     ap.add_argument("--workload", default="vgos-6bl-32x64-20000")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--copy-calibration-mb", type=int, default=0,
+                    help="after the timed steps, run one plain device copy (float32 "
+                         "multiply by 1) of this many MiB, to calibrate HBM counters")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU only: --gpus must be 1 "
@@ -131,6 +134,15 @@ def main():
             f"(fringe {tt['fringe_ms'] / 1e3:.2f} s, dedisperse {tt['dedisperse_ms'] / 1e3:.3f} s)")
     torch.cuda.synchronize()
     el = time.perf_counter() - t0
+    if args.copy_calibration_mb:
+        n = args.copy_calibration_mb * (1 << 20) // 4
+        src = torch.ones(n, dtype=torch.float32, device=dev)
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        torch.mul(src, 1.0, out=dst)
+        torch.cuda.synchronize()
+        log(f"copy calibration: read {n * 4} B, wrote {n * 4} B")
+        del src, dst
     n_det = len(s.candidates())
     groups = s.groups()
     n_rep = sum(1 for g in groups if g["reported"])

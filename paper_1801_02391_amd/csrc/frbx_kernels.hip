@@ -199,7 +199,7 @@ __global__ __launch_bounds__(kBlock) void dedisperse_kernel(DedisperseArgs a) {
   }
 }
 
-template <int J, int M>
+template <int J, int M, bool DUMP>
 __global__ __launch_bounds__(kBlock) void fringe_kernel(FringeArgs a) {
   using S = FringeShape<J, M>;
   constexpr int JA = S::JA, JB = S::JB, MA = S::MA, MB = S::MB, G = S::G, COLS = S::COLS;
@@ -215,7 +215,7 @@ __global__ __launch_bounds__(kBlock) void fringe_kernel(FringeArgs a) {
   // ---- which segment: spread consecutive segments over the 8 XCDs in
   // contiguous ranges so that overlapping segments share an L2.
   int dl, seg;
-  if (a.dump) {
+  if (DUMP) {
     dl = a.dump_dl;
     seg = a.dump_seg;
   } else {
@@ -366,7 +366,7 @@ __global__ __launch_bounds__(kBlock) void fringe_kernel(FringeArgs a) {
                 cv = v;
                 ck = kx;
               }
-              if (a.dump) a.dump[base + MA * kx] = v;
+              if constexpr (DUMP) a.dump[base + MA * kx] = v;
             });
             const int32_t ci = base + MA * ck;
             if (cv > best_v || (cv == best_v && ci < best_i)) {
@@ -394,7 +394,7 @@ __global__ __launch_bounds__(kBlock) void fringe_kernel(FringeArgs a) {
     red_i[t >> 6] = best_i;
   }
   __syncthreads();
-  if (t == 0 && !a.dump) {
+  if (t == 0 && !DUMP) {
     float bv = red_v[0];
     int32_t bi = red_i[0];
     for (int w = 1; w < kBlock / 64; ++w) {
@@ -514,15 +514,16 @@ hipError_t launch_dedisperse(const DedisperseArgs &a, hipStream_t s) {
   return hipGetLastError();
 }
 
-template <int J, int M>
+template <int J, int M, bool DUMP>
 static hipError_t launch_fringe_t(const FringeArgs &a, size_t lds, int grid, hipStream_t s) {
   (void)hipGetLastError();  // start from a clean error state
   if (lds > 64 * 1024) {
-    const hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(&fringe_kernel<J, M>),
-                                             hipFuncAttributeMaxDynamicSharedMemorySize, int(lds));
+    const hipError_t e =
+        hipFuncSetAttribute(reinterpret_cast<const void *>(&fringe_kernel<J, M, DUMP>),
+                            hipFuncAttributeMaxDynamicSharedMemorySize, int(lds));
     if (e != hipSuccess) return e;
   }
-  hipLaunchKernelGGL((fringe_kernel<J, M>), dim3(grid), dim3(kBlock), lds, s, a);
+  hipLaunchKernelGGL((fringe_kernel<J, M, DUMP>), dim3(grid), dim3(kBlock), lds, s, a);
   return hipGetLastError();
 }
 
@@ -554,7 +555,10 @@ struct LaunchFn {
   size_t lds;
   int grid;
   hipStream_t s;
-  template <int J, int M> hipError_t operator()() { return launch_fringe_t<J, M>(a, lds, grid, s); }
+  template <int J, int M> hipError_t operator()() {
+    return a.dump ? launch_fringe_t<J, M, true>(a, lds, grid, s)
+                  : launch_fringe_t<J, M, false>(a, lds, grid, s);
+  }
   hipError_t fail() { return hipErrorInvalidValue; }
 };
 
