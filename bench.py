@@ -23,6 +23,7 @@ if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 PEAK_FP32_TFLOPS = 157.3     # MI355X vector FP32 (packed), published
+PEAK_FP16_MFMA_TFLOPS = 2500.0  # MI355X dense FP16 matrix, published
 PEAK_HBM_GBS = 8000.0        # MI355X HBM3E, published
 
 
@@ -81,6 +82,10 @@ def main():
     ap.add_argument("--workload", default="vgos-6bl-32x64-20000")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--precision", default="f32", choices=["f32", "f16x3", "f16"],
+                    help="f32: vector-ALU FFT transforms; f16x3: MBD on the matrix cores "
+                         "as three float16 products (float32-grade); f16: one float16 "
+                         "product with complex32 (float16) stored cross spectra")
     ap.add_argument("--copy-calibration-mb", type=int, default=0,
                     help="after the timed steps, run one plain device copy (float32 "
                          "multiply by 1) of this many MiB, to calibrate HBM counters")
@@ -95,14 +100,18 @@ def main():
     from paper_1801_02391_amd import frbx
     from paper_1801_02391_amd import workloads as W
 
-    wl = W.get_workload(args.workload)
+    wl = W.get_workload(args.workload, search=dict(precision=args.precision))
     lay, srch = wl["layout"], wl["search"]
     log(f"generating {args.workload}")
     t0 = time.perf_counter()
     V, truth = W.generate(wl)
     log(f"generated {V.nbytes / 1e9:.2f} GB in {time.perf_counter() - t0:.1f} s")
     dev = torch.device("cuda:0")
-    Vt = torch.from_numpy(V).to(dev)
+    if args.precision == "f16":
+        Vt = torch.from_numpy(W.to_complex32(V)).to(dev)
+    else:
+        Vt = torch.from_numpy(V).to(dev)
+    del V
     torch.cuda.synchronize()
 
     s = frbx.Search(lay, device=0)
@@ -147,16 +156,24 @@ def main():
     groups = s.groups()
     n_rep = sum(1 for g in groups if g["reported"])
 
-    # dominant kernel: the fringe search (VALU-bound)
-    fpc = fringe_flops_per_cell(N, J, P, M)
+    # dominant kernel: the fringe search
     cells_per_unit = R * PJ * M
     avg_ms = tim["fringe_ms"] / max(1, tim["n_fringe"])
     units_per_launch = tim["fringe_units"] / max(1, tim["n_fringe"])
+    if args.precision == "f32":
+        # FFT-form FP32 work on the vector ALUs
+        fpc = fringe_flops_per_cell(N, J, P, M)
+        bound, peak, kern = "alu", PEAK_FP32_TFLOPS, "fringe_kernel"
+    else:
+        # matrix-core work: the real-embedded MBD GEMM, 2 x (2N) x (2M) flops
+        # per SBD bin, i.e. 8 N flops per cell per float16 product
+        fpc = 8 * N * (3 if args.precision == "f16x3" else 1)
+        bound, peak, kern = "mfma", PEAK_FP16_MFMA_TFLOPS, "fringe_mfma_kernel"
     flops_launch = units_per_launch * cells_per_unit * fpc
     achieved = flops_launch / (avg_ms * 1e-3) / 1e12 if avg_ms > 0 else 0.0
-    roof = {"bound": "alu", "achieved": round(achieved, 3), "peak": PEAK_FP32_TFLOPS,
-            "unit": "TFLOP/s", "frac": round(achieved / PEAK_FP32_TFLOPS, 4), "traffic": None,
-            "kernel": "fringe_kernel", "avg_launch_ms": round(avg_ms, 4),
+    roof = {"bound": bound, "achieved": round(achieved, 3), "peak": peak,
+            "unit": "TFLOP/s", "frac": round(achieved / peak, 4), "traffic": None,
+            "kernel": kern, "avg_launch_ms": round(avg_ms, 4),
             "flops_per_cell": round(fpc, 2), "units_per_launch": units_per_launch}
     # dedispersion kernel against HBM: read + write of one complex64 per
     # (DM trial, AP, channel)
@@ -178,7 +195,8 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f32",
+        "dtype": {"f32": "f32", "f16x3": "f32 (MBD as 3 x f16 MFMA)",
+                  "f16": "f16 storage + f16 MFMA, f32 accumulate"}[args.precision],
         "data": "synthetic",
         "config": {"workload": args.workload, "baselines": B, "if": N, "chan": J,
                    "frames": lay["n_frames"], "dm_trials": D, "rate_bins": R, "sbd_bins": PJ,
@@ -191,7 +209,8 @@ def main():
     }
     if not args.no_cpu_baseline:
         log("timing the oracle on a CPU sample")
-        out["cpu_baseline"] = cpu_baseline(wl, V, args.cpu_seconds)
+        Vs, _ = W.generate(wl, baselines=[0])
+        out["cpu_baseline"] = cpu_baseline(wl, Vs, args.cpu_seconds)
     print(json.dumps(out), flush=True)
 
 

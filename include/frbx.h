@@ -151,11 +151,36 @@ frbx_status frbx_set_windows(frbx_ctx *ctx, const int32_t *len_frames, int32_t n
 frbx_status frbx_set_detection(frbx_ctx *ctx, double threshold, int32_t n_win_min,
                                int32_t n_bl_min);
 
+/* Arithmetic of the fringe transform.
+ *   FRBX_PREC_F32       float32 segment sums, SBD and MBD transforms on the
+ *                       vector ALUs (in-register FFTs); powers exact in
+ *                       float32.
+ *   FRBX_PREC_F16X3     float32 segment sums and SBD transform; the MBD
+ *                       transform on the matrix cores as three float16
+ *                       products (high x high + high x low + low x high of a
+ *                       float16 high/low split of both operands, float32
+ *                       accumulation): products good to ~2^-21 relative.
+ *   FRBX_PREC_F16       as FRBX_PREC_F16X3 with one float16 product (inputs
+ *                       and DFT matrix rounded once to float16).
+ * The matrix-core forms need n_mbd = 256, n_chan >= 16 and n_if <= 32
+ * (FRBX_E_INVAL at frbx_run otherwise); their peak power keeps 19 mantissa
+ * bits of |G|^2 (the low bits carry the peak's position).  Operands are
+ * scaled by a power of two chosen from the largest input component so that
+ * float16 cannot overflow. */
+typedef enum { FRBX_PREC_F32 = 0, FRBX_PREC_F16X3 = 1, FRBX_PREC_F16 = 2 } frbx_precision;
+
+frbx_status frbx_set_precision(frbx_ctx *ctx, int32_t precision);
+
 /* Hand the cross spectra to the context: complex64 (re, im float32 pairs)
  * with layout [B][N][J][K].  is_device = 1: `vis` is a device pointer on the
  * context's device; it is borrowed and must stay valid and unchanged until
  * the next frbx_load or frbx_destroy.  is_device = 0: host memory, copied. */
 frbx_status frbx_load(frbx_ctx *ctx, const void *vis, int is_device);
+
+/* As frbx_load for cross spectra stored as complex32: (re, im) float16
+ * pairs, layout [B][N][J][K] (the storage form of the precision workloads).
+ * The search reads them into float32. */
+frbx_status frbx_load_f16(frbx_ctx *ctx, const void *vis, int is_device);
 
 /* Run the whole search on the context's stream and wait for it: dedispersion
  * and segment sums, fringe search and peak of every (baseline, DM trial,

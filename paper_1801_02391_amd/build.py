@@ -21,6 +21,8 @@ LIB = os.path.join(PKG, "libfrbx.so")
 ARCH = "gfx950"
 # Packed FP32 instructions are kept out of every device code object.
 DEVICE_FLAGS = ["-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops"]
+# Matrix-core results go straight to VGPRs (no accumulator read-back).
+KERNEL_FLAGS = ["-mllvm", "-amdgpu-mfma-vgpr-form=true"]
 COMMON = ["-std=c++17", "-fPIC", "-Wall", "-Wno-unused-function", "-Wno-unused-variable",
           f"--offload-arch={ARCH}"]
 
@@ -47,7 +49,7 @@ def build(verbose: bool = True) -> str:
     hipcc = _hipcc()
     objs = []
     k_obj = os.path.join(BUILD, "frbx_kernels.o")
-    _run([hipcc, "-c", "-O3", *COMMON, *DEVICE_FLAGS,
+    _run([hipcc, "-c", "-O3", *COMMON, *DEVICE_FLAGS, *KERNEL_FLAGS,
           os.path.join(CSRC, "frbx_kernels.hip"), "-o", k_obj], verbose)
     objs.append(k_obj)
     h_obj = os.path.join(BUILD, "frbx_host.o")

@@ -54,6 +54,7 @@ struct frbx_ctx {
   int n_rate = 1;
   double rate_step_req = 0.0;
   std::vector<int> windows{2, 4};
+  int precision = FRBX_PREC_F32;
   double threshold = 3.0;
   int n_win_min = 3, n_bl_min = 2;
 
@@ -65,12 +66,17 @@ struct frbx_ctx {
   int64_t seg_total = 0;
   double mbd_step = 0, t_amb = 0, rate_step = 0;
   std::vector<int32_t> mbd_row;
+  std::vector<int64_t> q_if;  // MBD lattice position of each IF
   std::vector<int> rate_off;
 
   // device memory
-  const float2 *d_vis = nullptr;
-  float2 *d_vis_own = nullptr;
+  const void *d_vis = nullptr;
+  void *d_vis_own = nullptr;
+  int vis_f16 = 0;
+  float vis_absmax = 0.f;
   bool loaded = false;
+  void *d_mfma_hi = nullptr, *d_mfma_lo = nullptr;
+  unsigned int *d_absmax = nullptr;
   int32_t *d_dk = nullptr;
   float2 *d_cal = nullptr, *d_rate = nullptr, *d_tw_sbd = nullptr, *d_pre = nullptr,
          *d_tw_mbd = nullptr;
@@ -150,6 +156,9 @@ struct frbx_ctx {
     hipSetDevice(device);
     for (hipEvent_t e : ev_pool) hipEventDestroy(e);
     dfree(d_vis_own);
+    dfree(d_mfma_hi);
+    dfree(d_mfma_lo);
+    dfree(d_absmax);
     dfree(d_dk);
     dfree(d_cal);
     dfree(d_rate);
@@ -279,6 +288,9 @@ frbx_status prepare(frbx_ctx *c) {
       return c->fail(FRBX_E_INVAL, "two IFs fall on the same MBD lattice point: raise n_mbd");
     c->mbd_row[qn] = n;
   }
+  c->q_if.assign(N, 0);
+  for (int qq = 0; qq < M; ++qq)
+    if (c->mbd_row[qq] < N) c->q_if[c->mbd_row[qq]] = qq;
   // rate grid (Eq. 4)
   int lmax = 1;
   for (int l : c->windows) lmax = std::max(lmax, l);
@@ -338,8 +350,49 @@ frbx_status prepare(frbx_ctx *c) {
   if ((s = up(c->d_tw_mbd, tw_mbd)) != FRBX_OK) return s;
   if ((s = up(c->d_row, c->mbd_row)) != FRBX_OK) return s;
   if ((s = up(c->d_cal, cal)) != FRBX_OK) return s;
+  if (c->precision != FRBX_PREC_F32) {
+    const int n_pass = c->precision == FRBX_PREC_F16X3 ? 3 : 1;
+    if (!frbx::fringe_mfma_supported(J, M, N, c->sbd_pad, n_pass))
+      return c->fail(FRBX_E_INVAL, "matrix-core precision needs n_mbd = 256, n_chan >= 16, n_if <= 32");
+    // Real-embedded DFT over the IF lattice as MFMA B operands: column tile
+    // t < 16 holds Re G for m in [16 t, 16 t + 16), t >= 16 holds Im G;
+    // row 2n multiplies Re X(n), row 2n + 1 multiplies Im X(n).  Stored in
+    // the per-lane order of v_mfma_f32_16x16x32_f16: lane l, element e of
+    // K-chunk kc is row 32 kc + 8 (l / 16) + e, column 16 t + l % 16.
+    const int NK = N <= 16 ? 1 : 2;
+    std::vector<_Float16> bh(size_t(32) * NK * 64 * 8), bl(bh.size());
+    for (int t = 0; t < 32; ++t)
+      for (int kc = 0; kc < NK; ++kc)
+        for (int ln = 0; ln < 64; ++ln)
+          for (int e = 0; e < 8; ++e) {
+            const int k = 32 * kc + 8 * (ln / 16) + e, n = k / 2, comp = k % 2;
+            const int m = 16 * (t % 16) + ln % 16;
+            double v = 0.0;
+            if (n < N) {
+              const double th = kTwoPi * double((c->q_if[n] * m) % M) / M;
+              const double cs = std::cos(th), sn = std::sin(th);
+              v = t < 16 ? (comp == 0 ? cs : sn) : (comp == 0 ? -sn : cs);
+            }
+            const size_t o = ((size_t(t) * NK + kc) * 64 + ln) * 8 + e;
+            bh[o] = static_cast<_Float16>(v);
+            bl[o] = static_cast<_Float16>(v - double(bh[o]));
+          }
+    if ((s = up(c->d_mfma_hi, bh)) != FRBX_OK) return s;
+    if ((s = up(c->d_mfma_lo, bl)) != FRBX_OK) return s;
+  }
   c->dirty = false;
   return FRBX_OK;
+}
+
+// float16 operand scale: a power of two with sqrt(2) J l_max max|component|
+// * scale <= 2^15, a bound on every SBD output |X(n, s)|
+float mfma_scale(const frbx_ctx *c) {
+  int lmax = 1;
+  for (int l : c->windows) lmax = std::max(lmax, l);
+  const double bound = std::sqrt(2.0) * c->J * lmax * double(c->vis_absmax);
+  if (!(bound > 0) || !std::isfinite(bound)) return 1.0f;
+  const int e = int(std::floor(std::log2(32768.0 / bound)));
+  return std::ldexp(1.0f, std::max(-100, std::min(100, e)));
 }
 
 template <typename T>
@@ -638,31 +691,56 @@ frbx_status frbx_set_detection(frbx_ctx *c, double threshold, int32_t n_win_min,
   return FRBX_OK;
 }
 
-frbx_status frbx_load(frbx_ctx *c, const void *vis, int is_device) {
+static frbx_status load_impl(frbx_ctx *c, const void *vis, int is_device, int f16) {
   if (!c) return FRBX_E_INVAL;
   if (!vis) return c->fail(FRBX_E_INVAL, "vis is NULL");
   if (hipSetDevice(c->device) != hipSuccess) return c->fail(FRBX_E_DEVICE, "hipSetDevice failed");
   c->have = false;
   c->loaded = false;
-  const size_t bytes = size_t(c->B) * c->N * c->J * size_t(c->K) * sizeof(float2);
+  const size_t n_cplx = size_t(c->B) * c->N * c->J * size_t(c->K);
+  const size_t bytes = n_cplx * (f16 ? 4 : 8);
   if (is_device) {
     hipPointerAttribute_t at;
     if (hipPointerGetAttributes(&at, vis) != hipSuccess || at.type != hipMemoryTypeDevice)
       return c->fail(FRBX_E_INVAL, "vis is not a device pointer");
     if (at.device != c->device) return c->fail(FRBX_E_INVAL, "vis is on another device");
     dfree(c->d_vis_own);
-    c->d_vis = static_cast<const float2 *>(vis);
+    c->d_vis = vis;
   } else {
     dfree(c->d_vis_own);
-    if (hipMalloc(reinterpret_cast<void **>(&c->d_vis_own), bytes) != hipSuccess)
+    if (hipMalloc(&c->d_vis_own, bytes) != hipSuccess)
       return c->fail(FRBX_E_NOMEM, "device allocation for the cross spectra failed");
     frbx_status s = c->hip(hipMemcpyAsync(c->d_vis_own, vis, bytes, hipMemcpyHostToDevice, c->stream),
                            "upload of cross spectra");
-    if (s == FRBX_OK) s = c->hip(hipStreamSynchronize(c->stream), "upload of cross spectra");
     if (s != FRBX_OK) return s;
     c->d_vis = c->d_vis_own;
   }
+  c->vis_f16 = f16;
+  // largest component, for the float16 operand scale of the matrix-core forms
+  if (!c->d_absmax && hipMalloc(reinterpret_cast<void **>(&c->d_absmax), sizeof(unsigned int)) != hipSuccess)
+    return c->fail(FRBX_E_NOMEM, "device allocation failed");
+  unsigned int am = 0;
+  frbx_status s = c->hip(hipMemsetAsync(c->d_absmax, 0, sizeof(unsigned int), c->stream), "memset");
+  if (s == FRBX_OK) s = c->hip(frbx::launch_absmax(c->d_vis, int64_t(n_cplx), f16, c->d_absmax, c->stream), "absmax launch");
+  if (s == FRBX_OK) s = c->hip(hipMemcpyAsync(&am, c->d_absmax, sizeof(am), hipMemcpyDeviceToHost, c->stream), "absmax");
+  if (s == FRBX_OK) s = c->hip(hipStreamSynchronize(c->stream), "load");
+  if (s != FRBX_OK) return s;
+  std::memcpy(&c->vis_absmax, &am, sizeof(float));
   c->loaded = true;
+  return FRBX_OK;
+}
+
+frbx_status frbx_load(frbx_ctx *c, const void *vis, int is_device) { return load_impl(c, vis, is_device, 0); }
+
+frbx_status frbx_load_f16(frbx_ctx *c, const void *vis, int is_device) { return load_impl(c, vis, is_device, 1); }
+
+frbx_status frbx_set_precision(frbx_ctx *c, int32_t precision) {
+  if (!c) return FRBX_E_INVAL;
+  if (precision != FRBX_PREC_F32 && precision != FRBX_PREC_F16X3 && precision != FRBX_PREC_F16)
+    return c->fail(FRBX_E_INVAL, "unknown precision");
+  c->precision = precision;
+  c->dirty = true;
+  c->have = false;
   return FRBX_OK;
 }
 
@@ -700,13 +778,18 @@ frbx_status frbx_run(frbx_ctx *c) {
     c->cross_cap = want_cap;
   }
   const int J = c->J, M = c->n_mbd;
-  const size_t lds = frbx::fringe_lds_bytes(J, M, c->N, c->sbd_pad);
+  const int n_pass = c->precision == FRBX_PREC_F16X3 ? 3 : 1;
+  const bool use_mfma = c->precision != FRBX_PREC_F32;
+  const size_t lds = use_mfma ? frbx::fringe_mfma_lds_bytes(J, c->N, c->sbd_pad, n_pass)
+                              : frbx::fringe_lds_bytes(J, M, c->N, c->sbd_pad);
+  const float scale = mfma_scale(c);
   if (S > 0 && c->k_eff > 0) {
     for (int b = 0; b < B; ++b) {
       for (int d0 = 0; d0 < D; d0 += c->dt) {
         const int ndt = std::min(c->dt, D - d0);
         frbx::DedisperseArgs da{};
-        da.vis = c->d_vis + size_t(b) * NJ * size_t(c->K);
+        da.vis = static_cast<const char *>(c->d_vis) + size_t(b) * NJ * size_t(c->K) * (c->vis_f16 ? 4 : 8);
+        da.in_f16 = c->vis_f16;
         da.n_frames = c->K;
         da.dk = c->d_dk;
         da.d0 = d0;
@@ -741,9 +824,14 @@ frbx_status frbx_run(frbx_ctx *c) {
         fa.power = c->d_power + (size_t(b) * D + d0) * S;
         fa.pidx = c->d_pidx + (size_t(b) * D + d0) * S;
         fa.dump = nullptr;
+        fa.mfma_b_hi = c->d_mfma_hi;
+        fa.mfma_b_lo = c->d_mfma_lo;
+        fa.mfma_scale = scale;
         sp = c->span_begin(0, int64_t(ndt) * S);
-        if ((s = c->hip(frbx::launch_fringe(J, M, fa, lds, int(ndt * S), c->stream), "fringe launch")) != FRBX_OK)
-          return s;
+        const hipError_t le = use_mfma
+                                  ? frbx::launch_fringe_mfma(J, c->N, n_pass, fa, lds, int(ndt * S), c->stream)
+                                  : frbx::launch_fringe(J, M, fa, lds, int(ndt * S), c->stream);
+        if ((s = c->hip(le, "fringe launch")) != FRBX_OK) return s;
         c->span_end(sp);
       }
     }
@@ -924,7 +1012,8 @@ frbx_status frbx_dump_segment(frbx_ctx *c, int32_t b, int32_t d, int32_t w, int6
   const size_t per_dm = size_t(c->k_eff) * NJ;
   if ((s = ensure(c, c->d_w, c->w_cap, std::max(c->w_cap, per_dm))) != FRBX_OK) return s;
   frbx::DedisperseArgs da{};
-  da.vis = c->d_vis + size_t(b) * NJ * size_t(c->K);
+  da.vis = static_cast<const char *>(c->d_vis) + size_t(b) * NJ * size_t(c->K) * (c->vis_f16 ? 4 : 8);
+  da.in_f16 = c->vis_f16;
   da.n_frames = c->K;
   da.dk = c->d_dk;
   da.d0 = d;
@@ -957,9 +1046,19 @@ frbx_status frbx_dump_segment(frbx_ctx *c, int32_t b, int32_t d, int32_t w, int6
   fa.dump = dev_out;
   fa.dump_dl = 0;
   fa.dump_seg = int(c->segoff[w] + q);
-  const size_t lds = frbx::fringe_lds_bytes(c->J, c->n_mbd, c->N, c->sbd_pad);
-  if ((s = c->hip(frbx::launch_fringe(c->J, c->n_mbd, fa, lds, 1, c->stream), "fringe launch")) != FRBX_OK)
-    return s;
+  const int n_pass = c->precision == FRBX_PREC_F16X3 ? 3 : 1;
+  fa.mfma_b_hi = c->d_mfma_hi;
+  fa.mfma_b_lo = c->d_mfma_lo;
+  fa.mfma_scale = mfma_scale(c);
+  hipError_t le;
+  if (c->precision != FRBX_PREC_F32) {
+    const size_t lds = frbx::fringe_mfma_lds_bytes(c->J, c->N, c->sbd_pad, n_pass);
+    le = frbx::launch_fringe_mfma(c->J, c->N, n_pass, fa, lds, 1, c->stream);
+  } else {
+    const size_t lds = frbx::fringe_lds_bytes(c->J, c->n_mbd, c->N, c->sbd_pad);
+    le = frbx::launch_fringe(c->J, c->n_mbd, fa, lds, 1, c->stream);
+  }
+  if ((s = c->hip(le, "fringe launch")) != FRBX_OK) return s;
   return c->hip(hipStreamSynchronize(c->stream), "dump");
 }
 

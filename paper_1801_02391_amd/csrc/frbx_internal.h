@@ -22,7 +22,9 @@ struct DevCrossing {
 // dedispersed, calibrated AP sequence W[dl][k][c] = cal[c] * V[c][k + dk[d][c]]
 // for k < k_eff and channel c = n * J + j.
 struct DedisperseArgs {
-  const float2 *vis;   // [NJ][K] of this baseline
+  const void *vis;     // [NJ][K] of this baseline: complex64, or complex32
+                       // (two float16) when in_f16
+  int32_t in_f16;
   int64_t n_frames;    // K
   const int32_t *dk;   // [D][NJ]
   int32_t d0;          // first DM trial of the tile
@@ -60,6 +62,13 @@ struct FringeArgs {
   float *dump;               // non-null: one segment, |G|^2 of every cell
   int32_t dump_dl;
   int32_t dump_seg;
+  // matrix-core form of the MBD transform: the real-embedded DFT matrix
+  // over the IF lattice as float16 MFMA B operands, [32 tiles][NK][64 lanes]
+  // x 8 halves, high part and (split form) low part; inputs are scaled by a
+  // power of two so that float16 cannot overflow
+  const void *mfma_b_hi;
+  const void *mfma_b_lo;
+  float mfma_scale;
 };
 
 struct StatsArgs {
@@ -86,5 +95,18 @@ hipError_t launch_fringe(int n_chan, int n_mbd, const FringeArgs &a, size_t lds_
 size_t fringe_lds_bytes(int n_chan, int n_mbd, int n_if, int sbd_pad);
 bool fringe_supported(int n_chan, int n_mbd, int n_if, int sbd_pad);
 hipError_t launch_stats(const StatsArgs &a, int rows, hipStream_t s);
+
+// matrix-core fringe kernel: n_pass = 1 (float16) or 3 (float16 high/low
+// split, float32-grade products); supports n_mbd = 256, n_chan >= 16,
+// n_if <= 32
+hipError_t launch_fringe_mfma(int n_chan, int n_if, int n_pass, const FringeArgs &a,
+                              size_t lds_bytes, int grid, hipStream_t s);
+size_t fringe_mfma_lds_bytes(int n_chan, int n_if, int sbd_pad, int n_pass);
+bool fringe_mfma_supported(int n_chan, int n_mbd, int n_if, int sbd_pad, int n_pass);
+
+// max(|re|, |im|) over n complex values (float32 or float16 pairs) into
+// *out (float bits, caller zeroes it first)
+hipError_t launch_absmax(const void *vis, int64_t n, int in_f16, unsigned int *out,
+                         hipStream_t s);
 
 }  // namespace frbx

@@ -19,6 +19,7 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <algorithm>
 #include <cmath>
 #include <type_traits>
 
@@ -174,7 +175,84 @@ __host__ __device__ inline void fringe_lds_plan(int n_if, int sbd_pad, int &x_of
   total = t_off + sbd_pad * J;
 }
 
+
+// ------------------------------------------------------- shared fringe steps
+// Which segment a work-group handles.  Work-groups are dealt to the 8 XCDs
+// round-robin; when the grid splits evenly, XCD x gets the contiguous range
+// [x nb/8, (x+1) nb/8) so that overlapping segments share an L2.
+__device__ __forceinline__ void block_segment(const FringeArgs &a, bool dump, int &dl, int &seg) {
+  if (dump) {
+    dl = a.dump_dl;
+    seg = a.dump_seg;
+    return;
+  }
+  const int nb = gridDim.x;
+  const int bx = blockIdx.x;
+  const int lb = (nb & 7) == 0 ? (bx & 7) * (nb >> 3) + (bx >> 3) : bx;
+  dl = lb / a.seg_total;
+  seg = lb - dl * a.seg_total;
+}
+
+// Segment sum of Eq. 3 with the Eq. 4 rate rotation about the window centre
+// for rate bin r: y[i1] = sum_u ph[r][n1][u] W[k0 + u][n1][JB i1 + i2], with
+// the j = 0 point excluded from the fit (Sec. 2.3).
+template <int JA, int JB>
+__device__ __forceinline__ void segment_sum(float2 (&y)[JA], const float2 *wd, const float2 *rph,
+                                            int r, int N, int J, int l, int R, bool act, int n1,
+                                            int i2s) {
+  static_for<0, JA>([&](auto i) { y[decltype(i)::value] = make_float2(0.f, 0.f); });
+  if (!act) return;
+  const int NJ = N * J;
+  const float2 *src = wd + n1 * J + i2s;
+  const float2 *ph = rph + (r * N + n1) * l;
+  for (int u = 0; u < l; ++u) {
+    if (R > 1) {
+      const float2 p = ph[u];
+      static_for<0, JA>([&](auto i) {
+        constexpr int ii = decltype(i)::value;
+        const float2 v = src[int64_t(u) * NJ + JB * ii];
+        y[ii] = cadd(y[ii], cmul(v, p));
+      });
+    } else {
+      static_for<0, JA>([&](auto i) {
+        constexpr int ii = decltype(i)::value;
+        y[ii] = cadd(y[ii], src[int64_t(u) * NJ + JB * ii]);
+      });
+    }
+  }
+  if (i2s == 0) y[0] = make_float2(0.f, 0.f);
+}
+
+// SBD pass 1 of tile c: x[i1] = y[i1] w_{P JA}^{i1 c}; JA-point DFT over i1;
+// twiddle w_PJ^{i2 (c + P k1)}; store transposed T[n][k1][i2].
+template <int JA, int JB>
+__device__ __forceinline__ void sbd_pass1(const float2 (&y)[JA], const float2 *pre,
+                                          const float2 *TW, float2 *Sc, int c, int P, int PJ,
+                                          bool act, int n1, int i2s) {
+  if (!act) return;
+  float2 x[JA];
+  static_for<0, JA>([&](auto i) {
+    constexpr int ii = decltype(i)::value;
+    x[ii] = cmul(y[ii], pre[c * JA + ii]);
+  });
+  dft<JA>(x);
+  static_for<0, JA>([&](auto k) {
+    constexpr int kk = decltype(k)::value;
+    const float2 w = TW[(i2s * (c + P * kk)) & (PJ - 1)];
+    Sc[(n1 * JA + kk) * (JB + 1) + i2s] = cmul(x[kk], w);
+  });
+}
+
 // ---------------------------------------------------------------- kernels
+__device__ __forceinline__ float2 load_vis(const void *p, int64_t i, bool f16) {
+  if (f16) {
+    const _Float16 *h = static_cast<const _Float16 *>(p) + 2 * i;
+    return make_float2(float(h[0]), float(h[1]));
+  }
+  return static_cast<const float2 *>(p)[i];
+}
+
+template <bool F16>
 __global__ __launch_bounds__(kBlock) void dedisperse_kernel(DedisperseArgs a) {
   __shared__ float2 tile[64][65];
   const int64_t kt = int64_t(blockIdx.x) * 64;
@@ -186,7 +264,7 @@ __global__ __launch_bounds__(kBlock) void dedisperse_kernel(DedisperseArgs a) {
     const int c = ct + i;
     const int64_t k = kt + lane;
     float2 v = make_float2(0.f, 0.f);
-    if (c < a.nj && k < a.k_eff) v = a.vis[int64_t(c) * a.n_frames + k + dkd[c]];
+    if (c < a.nj && k < a.k_eff) v = load_vis(a.vis, int64_t(c) * a.n_frames + k + dkd[c], F16);
     tile[i][lane] = v;
   }
   __syncthreads();
@@ -215,18 +293,7 @@ __global__ __launch_bounds__(kBlock) void fringe_kernel(FringeArgs a) {
   // ---- which segment: spread consecutive segments over the 8 XCDs in
   // contiguous ranges so that overlapping segments share an L2.
   int dl, seg;
-  if (DUMP) {
-    dl = a.dump_dl;
-    seg = a.dump_seg;
-  } else {
-    // work-groups are dealt to the XCDs round-robin; when the grid splits
-    // evenly, give XCD x the contiguous range [x nb/8, (x+1) nb/8)
-    const int nb = gridDim.x;
-    const int bx = blockIdx.x;
-    const int lb = (nb & 7) == 0 ? (bx & 7) * (nb >> 3) + (bx >> 3) : bx;
-    dl = lb / a.seg_total;
-    seg = lb - dl * a.seg_total;
-  }
+  block_segment(a, DUMP, dl, seg);
   int wi = 0;
   while (wi + 1 < a.n_win && a.win_off[wi + 1] <= seg) ++wi;
   const int l = a.win_len[wi];
@@ -268,48 +335,12 @@ __global__ __launch_bounds__(kBlock) void fringe_kernel(FringeArgs a) {
   int32_t best_i = 0x7fffffff;
 
   for (int r = 0; r < R; ++r) {
-    // segment sum of Eq. 3 with the Eq. 4 rate rotation about the window
-    // centre; channel j = JB * i1 + i2s of IF n1
     float2 y[JA];
-    static_for<0, JA>([&](auto i) { y[decltype(i)::value] = make_float2(0.f, 0.f); });
-    if (s_p1) {
-      const float2 *src = wd + n1 * J + i2s;
-      const float2 *ph = rph + (r * N + n1) * l;
-      for (int u = 0; u < l; ++u) {
-        if (R > 1) {
-          const float2 p = ph[u];
-          static_for<0, JA>([&](auto i) {
-            constexpr int ii = decltype(i)::value;
-            const float2 v = src[int64_t(u) * NJ + JB * ii];
-            y[ii] = cadd(y[ii], cmul(v, p));
-          });
-        } else {
-          static_for<0, JA>([&](auto i) {
-            constexpr int ii = decltype(i)::value;
-            y[ii] = cadd(y[ii], src[int64_t(u) * NJ + JB * ii]);
-          });
-        }
-      }
-      if (i2s == 0) y[0] = make_float2(0.f, 0.f);  // j = 0 takes no part (Sec. 2.3)
-    }
+    segment_sum<JA, JB>(y, wd, rph, r, N, J, l, R, s_p1, n1, i2s);
 
     for (int c = 0; c < P; ++c) {
       __syncthreads();
-      // SBD pass 1: x[i1] = y[i1] w_{P JA}^{i1 c}; JA-point DFT over i1;
-      // twiddle w_PJ^{i2 (c + P k1)}; store transposed T[n][k1][i2].
-      if (s_p1) {
-        float2 x[JA];
-        static_for<0, JA>([&](auto i) {
-          constexpr int ii = decltype(i)::value;
-          x[ii] = cmul(y[ii], a.pre_sbd[c * JA + ii]);
-        });
-        dft<JA>(x);
-        static_for<0, JA>([&](auto k) {
-          constexpr int kk = decltype(k)::value;
-          const float2 w = TW[(i2s * (c + P * kk)) & (PJ - 1)];
-          Sc[(n1 * JA + kk) * (JB + 1) + i2s] = cmul(x[kk], w);
-        });
-      }
+      sbd_pass1<JA, JB>(y, a.pre_sbd, TW, Sc, c, P, PJ, s_p1, n1, i2s);
       __syncthreads();
       // SBD pass 2: JB-point DFT over i2 -> X[n][a = k1 + JA k2], the SBD
       // bin s' = c + P a of the standard (unshifted) transform.
@@ -504,13 +535,238 @@ __global__ __launch_bounds__(kBlock) void stats_kernel(StatsArgs a) {
   }
 }
 
+
+// ------------------------------------------------ matrix-core fringe kernel
+// The MBD transform of Eq. 5 as a real-embedded complex GEMM on the gfx950
+// matrix cores: for each SBD column s, G(s, m) = sum_n X(n, s) w_M^{q_n m};
+// with A[s][2n + {0,1}] = (Re, Im) X(n, s) and the constant B operand
+// B[2n][m] = (cos, -sin), B[2n+1][m] = (sin, cos) (Re and Im column blocks),
+// one v_mfma_f32_16x16x32_f16 per (16 SBD rows, 16 MBD columns, 32 K).
+// The segment sum and the SBD transform are the float32 steps above; the
+// SBD output is scaled (power of two), rounded to float16 (and, in the
+// 3-pass form, its residual to a second float16) and staged in LDS in the
+// A-operand layout.  Each of the 4 waves owns 64 MBD columns and keeps
+// their B operands in registers for the kernel's life.
+typedef _Float16 h8_t __attribute__((ext_vector_type(8)));
+typedef _Float16 h2_t __attribute__((ext_vector_type(2)));
+typedef float f4_t __attribute__((ext_vector_type(4)));
+
+template <int J, int NK>
+__host__ __device__ inline void mfma_lds_plan(int n_if, int sbd_pad, int n_pass, int &t_off,
+                                              int &a_off, int &total_bytes) {
+  constexpr int JA = Split<J>::A, JB = Split<J>::B;
+  constexpr int AS = 32 * NK + 8;
+  const int t_bytes = n_if * JA * (JB + 1) * 8;
+  const int tw_bytes = sbd_pad * J * 8;
+  t_off = t_bytes;                               // TW after the transpose scratch
+  a_off = (t_bytes + tw_bytes + 15) & ~15;       // A tiles, 16-byte aligned
+  total_bytes = a_off + (n_pass == 3 ? 2 : 1) * J * AS * 2;
+}
+
+template <int J, int NK, int NP, bool DUMP>
+__global__ __launch_bounds__(kBlock) void fringe_mfma_kernel(FringeArgs a) {
+  constexpr int M = 256;
+  constexpr int JA = Split<J>::A, JB = Split<J>::B;
+  constexpr int AS = 32 * NK + 8;   // A row stride in halves (+16 B against bank conflicts)
+  constexpr int NSB = J / 16;       // 16-row SBD blocks per tile
+  extern __shared__ float2 lds[];
+  __shared__ float red_v[kBlock / 64];
+  __shared__ int32_t red_i[kBlock / 64];
+
+  const int N = a.n_if, R = a.n_rate, P = a.sbd_pad;
+  const int PJ = P * J;
+  const int NJ = N * J;
+  const int t = threadIdx.x, wave = t >> 6, lane = t & 63;
+
+  int dl, seg;
+  block_segment(a, DUMP, dl, seg);
+  int wi = 0;
+  while (wi + 1 < a.n_win && a.win_off[wi + 1] <= seg) ++wi;
+  const int l = a.win_len[wi];
+  const int q = seg - a.win_off[wi];
+  const int64_t k0 = int64_t(q) * a.win_hop[wi];
+  const float2 *wd = a.w + int64_t(dl) * a.w_dm_stride + k0 * NJ;
+  const float2 *rph = a.rate_ph + a.rate_off[wi];
+
+  int t_off, a_off, total;
+  mfma_lds_plan<J, NK>(N, P, NP, t_off, a_off, total);
+  float2 *Sc = lds;
+  float2 *TW = reinterpret_cast<float2 *>(reinterpret_cast<char *>(lds) + t_off);
+  _Float16 *Ahi = reinterpret_cast<_Float16 *>(reinterpret_cast<char *>(lds) + a_off);
+  _Float16 *Alo = Ahi + J * AS;
+
+  for (int i = t; i < PJ; i += kBlock) TW[i] = a.tw_sbd[i];
+  for (int i = t; i < (NP == 3 ? 2 : 1) * J * AS; i += kBlock) Ahi[i] = _Float16(0.0f);
+
+  // B operands of this wave: Re tiles 4 wave + p and Im tiles 16 + 4 wave + p
+  h8_t bh[8][NK], bl[8][NK];
+  {
+    const h8_t *srch = static_cast<const h8_t *>(a.mfma_b_hi);
+    const h8_t *srcl = static_cast<const h8_t *>(a.mfma_b_lo);
+    static_for<0, 8>([&](auto qq) {
+      constexpr int p8 = decltype(qq)::value;
+      const int tile = p8 < 4 ? 4 * wave + p8 : 16 + 4 * wave + (p8 - 4);
+      static_for<0, NK>([&](auto kk) {
+        constexpr int kc = decltype(kk)::value;
+        bh[p8][kc] = srch[(tile * NK + kc) * 64 + lane];
+        if constexpr (NP == 3) bl[p8][kc] = srcl[(tile * NK + kc) * 64 + lane];
+      });
+    });
+  }
+  const float scale = a.mfma_scale;
+
+  const bool s_p1 = t < N * JB;
+  const int n1 = t / JB, i2s = t - (t / JB) * JB;
+
+  float best_v = -1.0f;
+  int32_t best_i = 0x7fffffff;
+  unsigned best_key = 0u;
+  int best_blk = 0;
+
+  for (int r = 0; r < R; ++r) {
+    float2 y[JA];
+    segment_sum<JA, JB>(y, wd, rph, r, N, J, l, R, s_p1, n1, i2s);
+    for (int c = 0; c < P; ++c) {
+      __syncthreads();
+      sbd_pass1<JA, JB>(y, a.pre_sbd, TW, Sc, c, P, PJ, s_p1, n1, i2s);
+      __syncthreads();
+      // SBD pass 2 -> A rows a = k1 + JA k2 (SBD bin s' = c + P a), columns 2n, 2n+1
+      for (int v = t; v < N * JA; v += kBlock) {
+        const int n2 = v / JA, k1 = v - (v / JA) * JA;
+        float2 z[JB];
+        static_for<0, JB>([&](auto i) {
+          constexpr int ii = decltype(i)::value;
+          z[ii] = Sc[(n2 * JA + k1) * (JB + 1) + ii];
+        });
+        dft<JB>(z);
+        static_for<0, JB>([&](auto k) {
+          constexpr int kk = decltype(k)::value;
+          const float xr = z[kk].x * scale, xi = z[kk].y * scale;
+          h2_t hi;
+          hi.x = _Float16(xr);
+          hi.y = _Float16(xi);
+          const int o = (k1 + JA * kk) * AS + 2 * n2;
+          *reinterpret_cast<h2_t *>(Ahi + o) = hi;
+          if constexpr (NP == 3) {
+            h2_t lo;
+            lo.x = _Float16(xr - float(hi.x));
+            lo.y = _Float16(xi - float(hi.y));
+            *reinterpret_cast<h2_t *>(Alo + o) = lo;
+          }
+        });
+      }
+      __syncthreads();
+      // MBD on the matrix cores, 16 SBD rows at a time
+      for (int sb = 0; sb < NSB; ++sb) {
+        h8_t ah[NK], al[NK];
+        const int arow = (16 * sb + (lane & 15)) * AS + 8 * (lane >> 4);
+        static_for<0, NK>([&](auto kk) {
+          constexpr int kc = decltype(kk)::value;
+          ah[kc] = *reinterpret_cast<const h8_t *>(Ahi + arow + 32 * kc);
+          if constexpr (NP == 3) al[kc] = *reinterpret_cast<const h8_t *>(Alo + arow + 32 * kc);
+        });
+        // peak key of this lane's 16 cells: |G|^2 with its 4 lowest mantissa
+        // bits replaced by (15 - slot), so one unsigned max keeps the value
+        // (to 2^-19 relative) and the lowest slot among equal values
+        unsigned kmax = 0u;
+        static_for<0, 4>([&](auto pp) {
+          constexpr int p = decltype(pp)::value;
+          f4_t gr = {0.f, 0.f, 0.f, 0.f}, gi = {0.f, 0.f, 0.f, 0.f};
+          static_for<0, NK>([&](auto kk) {
+            constexpr int kc = decltype(kk)::value;
+            if constexpr (NP == 3) {
+              gr = __builtin_amdgcn_mfma_f32_16x16x32_f16(al[kc], bh[p][kc], gr, 0, 0, 0);
+              gi = __builtin_amdgcn_mfma_f32_16x16x32_f16(al[kc], bh[4 + p][kc], gi, 0, 0, 0);
+              gr = __builtin_amdgcn_mfma_f32_16x16x32_f16(ah[kc], bl[p][kc], gr, 0, 0, 0);
+              gi = __builtin_amdgcn_mfma_f32_16x16x32_f16(ah[kc], bl[4 + p][kc], gi, 0, 0, 0);
+            }
+            gr = __builtin_amdgcn_mfma_f32_16x16x32_f16(ah[kc], bh[p][kc], gr, 0, 0, 0);
+            gi = __builtin_amdgcn_mfma_f32_16x16x32_f16(ah[kc], bh[4 + p][kc], gi, 0, 0, 0);
+          });
+          static_for<0, 4>([&](auto ii) {
+            constexpr int i = decltype(ii)::value;
+            const float v = gr[i] * gr[i] + gi[i] * gi[i];
+            const unsigned key = (__float_as_uint(v) & 0xFFFFFFF0u) | unsigned(15 - (p * 4 + i));
+            kmax = kmax > key ? kmax : key;
+            if constexpr (DUMP) {
+              const int arow_i = 16 * sb + 4 * (lane >> 4) + i;
+              const int s = (c + P * arow_i + (PJ >> 1)) & (PJ - 1);
+              const int m = (16 * (4 * wave + p) + (lane & 15) + (M >> 1)) & (M - 1);
+              a.dump[(r * PJ + s) * M + m] = v / (scale * scale);
+            }
+          });
+        });
+        const float bv = __uint_as_float(kmax & 0xFFFFFFF0u);
+        if (bv > best_v) {
+          best_v = bv;
+          best_key = kmax;
+          best_blk = (r * P + c) * NSB + sb;
+        }
+      }
+    }
+  }
+  // packed index of this lane's best cell
+  if (best_v >= 0.0f) {
+    const int slot = 15 - int(best_key & 15u);
+    const int p = slot >> 2, i = slot & 3;
+    const int sb = best_blk % NSB, rc = best_blk / NSB;
+    const int c = rc % P, r = rc / P;
+    const int arow_i = 16 * sb + 4 * (lane >> 4) + i;
+    const int s = (c + P * arow_i + (PJ >> 1)) & (PJ - 1);
+    const int m = (16 * (4 * wave + p) + (lane & 15) + (M >> 1)) & (M - 1);
+    best_i = (r * PJ + s) * M + m;
+  }
+
+  for (int off = 32; off > 0; off >>= 1) {
+    const float ov = __shfl_xor(best_v, off, 64);
+    const int32_t oi = __shfl_xor(best_i, off, 64);
+    if (ov > best_v || (ov == best_v && oi < best_i)) {
+      best_v = ov;
+      best_i = oi;
+    }
+  }
+  if (lane == 0) {
+    red_v[wave] = best_v;
+    red_i[wave] = best_i;
+  }
+  __syncthreads();
+  if (t == 0 && !DUMP) {
+    float bv = red_v[0];
+    int32_t bi = red_i[0];
+    for (int w = 1; w < kBlock / 64; ++w) {
+      if (red_v[w] > bv || (red_v[w] == bv && red_i[w] < bi)) {
+        bv = red_v[w];
+        bi = red_i[w];
+      }
+    }
+    const int64_t o = int64_t(dl) * a.seg_total + seg;
+    a.power[o] = bv >= 0.0f ? sqrtf(bv) / scale : __builtin_nanf("");
+    a.pidx[o] = bv >= 0.0f ? bi : -1;
+  }
+}
+
+__global__ __launch_bounds__(kBlock) void absmax_kernel(const void *vis, int64_t n, int in_f16,
+                                                        unsigned int *out) {
+  float m = 0.f;
+  for (int64_t i = int64_t(blockIdx.x) * kBlock + threadIdx.x; i < n;
+       i += int64_t(gridDim.x) * kBlock) {
+    const float2 v = load_vis(vis, i, in_f16 != 0);
+    m = fmaxf(m, fmaxf(fabsf(v.x), fabsf(v.y)));
+  }
+  for (int off = 32; off > 0; off >>= 1) m = fmaxf(m, __shfl_xor(m, off, 64));
+  if ((threadIdx.x & 63) == 0) atomicMax(out, __float_as_uint(m));
+}
+
 }  // namespace
 
 // ---------------------------------------------------------------- launchers
 hipError_t launch_dedisperse(const DedisperseArgs &a, hipStream_t s) {
   (void)hipGetLastError();
   dim3 grid(unsigned((a.k_eff + 63) / 64), unsigned((a.nj + 63) / 64), unsigned(a.n_dt));
-  hipLaunchKernelGGL(dedisperse_kernel, grid, dim3(kBlock), 0, s, a);
+  if (a.in_f16)
+    hipLaunchKernelGGL(dedisperse_kernel<true>, grid, dim3(kBlock), 0, s, a);
+  else
+    hipLaunchKernelGGL(dedisperse_kernel<false>, grid, dim3(kBlock), 0, s, a);
   return hipGetLastError();
 }
 
@@ -600,6 +856,89 @@ hipError_t launch_stats(const StatsArgs &a, int rows, hipStream_t s) {
   if (rows <= 0) return hipSuccess;
   (void)hipGetLastError();
   hipLaunchKernelGGL(stats_kernel, dim3(rows), dim3(kBlock), 0, s, a);
+  return hipGetLastError();
+}
+
+
+template <int J, int NK, int NP>
+static hipError_t launch_mfma_t(const FringeArgs &a, size_t lds, int grid, hipStream_t s) {
+  (void)hipGetLastError();
+  if (a.dump) {
+    if (lds > 64 * 1024) {
+      const hipError_t e = hipFuncSetAttribute(
+          reinterpret_cast<const void *>(&fringe_mfma_kernel<J, NK, NP, true>),
+          hipFuncAttributeMaxDynamicSharedMemorySize, int(lds));
+      if (e != hipSuccess) return e;
+    }
+    hipLaunchKernelGGL((fringe_mfma_kernel<J, NK, NP, true>), dim3(grid), dim3(kBlock), lds, s, a);
+  } else {
+    if (lds > 64 * 1024) {
+      const hipError_t e = hipFuncSetAttribute(
+          reinterpret_cast<const void *>(&fringe_mfma_kernel<J, NK, NP, false>),
+          hipFuncAttributeMaxDynamicSharedMemorySize, int(lds));
+      if (e != hipSuccess) return e;
+    }
+    hipLaunchKernelGGL((fringe_mfma_kernel<J, NK, NP, false>), dim3(grid), dim3(kBlock), lds, s, a);
+  }
+  return hipGetLastError();
+}
+
+template <int J>
+static hipError_t launch_mfma_j(int nk, int np, const FringeArgs &a, size_t lds, int grid,
+                                hipStream_t s) {
+  if (nk == 1) return np == 3 ? launch_mfma_t<J, 1, 3>(a, lds, grid, s) : launch_mfma_t<J, 1, 1>(a, lds, grid, s);
+  if (nk == 2) return np == 3 ? launch_mfma_t<J, 2, 3>(a, lds, grid, s) : launch_mfma_t<J, 2, 1>(a, lds, grid, s);
+  return hipErrorInvalidValue;
+}
+
+static int mfma_nk(int n_if) { return n_if <= 16 ? 1 : n_if <= 32 ? 2 : 0; }
+
+hipError_t launch_fringe_mfma(int n_chan, int n_if, int n_pass, const FringeArgs &a, size_t lds,
+                              int grid, hipStream_t s) {
+  const int nk = mfma_nk(n_if);
+  switch (n_chan) {
+    case 16: return launch_mfma_j<16>(nk, n_pass, a, lds, grid, s);
+    case 32: return launch_mfma_j<32>(nk, n_pass, a, lds, grid, s);
+    case 64: return launch_mfma_j<64>(nk, n_pass, a, lds, grid, s);
+    case 128: return launch_mfma_j<128>(nk, n_pass, a, lds, grid, s);
+    case 256: return launch_mfma_j<256>(nk, n_pass, a, lds, grid, s);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+size_t fringe_mfma_lds_bytes(int n_chan, int n_if, int sbd_pad, int n_pass) {
+  int to, ao, tot;
+  const int nk = mfma_nk(n_if);
+  auto plan = [&](auto jc) {
+    constexpr int J = decltype(jc)::value;
+    if (nk == 1) mfma_lds_plan<J, 1>(n_if, sbd_pad, n_pass, to, ao, tot);
+    else mfma_lds_plan<J, 2>(n_if, sbd_pad, n_pass, to, ao, tot);
+  };
+  switch (n_chan) {
+    case 16: plan(std::integral_constant<int, 16>{}); break;
+    case 32: plan(std::integral_constant<int, 32>{}); break;
+    case 64: plan(std::integral_constant<int, 64>{}); break;
+    case 128: plan(std::integral_constant<int, 128>{}); break;
+    case 256: plan(std::integral_constant<int, 256>{}); break;
+    default: return 0;
+  }
+  return size_t(tot);
+}
+
+bool fringe_mfma_supported(int n_chan, int n_mbd, int n_if, int sbd_pad, int n_pass) {
+  if (n_mbd != 256 || (n_pass != 1 && n_pass != 3) || mfma_nk(n_if) == 0) return false;
+  if (n_chan < 16 || n_chan > 256) return false;
+  const int JB = n_chan >= 256 ? 16 : n_chan >= 64 ? 8 : 4;
+  if (n_if * JB > kBlock) return false;
+  const size_t b = fringe_mfma_lds_bytes(n_chan, n_if, sbd_pad, n_pass);
+  return b > 0 && b <= 150 * 1024;
+}
+
+hipError_t launch_absmax(const void *vis, int64_t n, int in_f16, unsigned int *out, hipStream_t s) {
+  (void)hipGetLastError();
+  const int64_t blocks = std::min<int64_t>(4096, (n + kBlock - 1) / kBlock);
+  if (blocks <= 0) return hipSuccess;
+  hipLaunchKernelGGL(absmax_kernel, dim3(unsigned(blocks)), dim3(kBlock), 0, s, vis, n, in_f16, out);
   return hipGetLastError();
 }
 

@@ -16,6 +16,8 @@ _LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libfrbx.so
 _lib = None
 
 OK, E_INVAL, E_STATE, E_RANGE, E_NOMEM, E_DEVICE = range(6)
+PREC_F32, PREC_F16X3, PREC_F16 = 0, 1, 2
+PRECISIONS = {"f32": PREC_F32, "f16x3": PREC_F16X3, "f16": PREC_F16}
 _STATUS = {0: "OK", 1: "E_INVAL", 2: "E_STATE", 3: "E_RANGE", 4: "E_NOMEM", 5: "E_DEVICE"}
 
 
@@ -66,6 +68,8 @@ _SIGS = {
     "frbx_set_windows": ([_P, _P, C.c_int32], C.c_int),
     "frbx_set_detection": ([_P, C.c_double, C.c_int32, C.c_int32], C.c_int),
     "frbx_load": ([_P, _P, C.c_int], C.c_int),
+    "frbx_load_f16": ([_P, _P, C.c_int], C.c_int),
+    "frbx_set_precision": ([_P, C.c_int32], C.c_int),
     "frbx_run": ([_P], C.c_int),
     "frbx_get_segments": ([_P, _P, _P, _P, _P], C.c_int),
     "frbx_get_ap_offsets": ([_P, _P, C.c_int64, _P], C.c_int),
@@ -217,6 +221,9 @@ class Search:
         self._chk(L.frbx_set_windows(h, _ptr(w), len(w)), "set_windows")
         self._chk(L.frbx_set_detection(h, search["threshold"], search["n_win_min"],
                                        search["n_bl_min"]), "set_detection")
+        prec = search.get("precision", "f32")
+        self._chk(L.frbx_set_precision(h, PRECISIONS[prec] if isinstance(prec, str) else int(prec)),
+                  "set_precision")
         if tau0_us is not None or phi0_rad is not None:
             t = None if tau0_us is None else np.ascontiguousarray(tau0_us, dtype=np.float64)
             p = None if phi0_rad is None else np.ascontiguousarray(phi0_rad, dtype=np.float64)
@@ -224,19 +231,27 @@ class Search:
         self.search = dict(search)
 
     def load(self, vis):
-        """vis: complex64 [B][N][J][K] as a torch tensor (on this device: borrowed)
-        or a numpy array (copied)."""
+        """vis: [B][N][J][K] complex64, or float16 [B][N][J][K][2] (re, im), as
+        a torch tensor (on this device: borrowed) or a numpy array (copied)."""
         torch = self._torch
         if isinstance(vis, torch.Tensor):
-            if vis.dtype != torch.complex64 or not vis.is_contiguous():
-                raise FrbxError(E_INVAL, "vis must be a contiguous complex64 tensor")
-            if vis.device.type != "cuda":
-                raise FrbxError(E_INVAL, "vis tensor must live on the GPU")
+            if not vis.is_contiguous() or vis.device.type != "cuda":
+                raise FrbxError(E_INVAL, "vis must be a contiguous tensor on the GPU")
+            if vis.dtype == torch.complex64:
+                fn = lib().frbx_load
+            elif vis.dtype == torch.float16 and vis.shape[-1] == 2:
+                fn = lib().frbx_load_f16
+            else:
+                raise FrbxError(E_INVAL, "vis must be complex64 or float16 (re, im) pairs")
             self._vis = vis
-            self._chk(lib().frbx_load(self._h, _P(vis.data_ptr()), 1), "load")
+            self._chk(fn(self._h, _P(vis.data_ptr()), 1), "load")
         else:
-            a = np.ascontiguousarray(vis, dtype=np.complex64)
-            self._chk(lib().frbx_load(self._h, _ptr(a), 0), "load")
+            if vis.dtype == np.float16:
+                a = np.ascontiguousarray(vis)
+                self._chk(lib().frbx_load_f16(self._h, _ptr(a), 0), "load")
+            else:
+                a = np.ascontiguousarray(vis, dtype=np.complex64)
+                self._chk(lib().frbx_load(self._h, _ptr(a), 0), "load")
 
     def run(self):
         self._chk(lib().frbx_run(self._h), "run")

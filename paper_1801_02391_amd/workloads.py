@@ -106,6 +106,19 @@ _WORKLOADS = {
 }
 
 
+def to_complex32(V):
+    """complex64 [..] -> float16 [.., 2] (re, im): the complex32 storage form."""
+    out = np.empty(V.shape + (2,), dtype=np.float16)
+    out[..., 0] = V.real
+    out[..., 1] = V.imag
+    return out
+
+
+def from_complex32(H):
+    """float16 [.., 2] -> the complex64 values it stores exactly."""
+    return (H[..., 0].astype(np.float32) + 1j * H[..., 1].astype(np.float32)).astype(np.complex64)
+
+
 def workload_names():
     return list(_WORKLOADS)
 

@@ -18,7 +18,7 @@ ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 
 def _header_names():
     src = open(os.path.join(ROOT, "include", "frbx.h")).read()
-    return sorted(set(re.findall(r"\b(frbx_[a-z_]+)\s*\(", src)))
+    return sorted(set(re.findall(r"\b(frbx_[a-z_0-9]+)\s*\(", src)))
 
 
 def test_library_exports_every_declared_symbol():
