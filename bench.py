@@ -74,46 +74,19 @@ def cpu_baseline(wl, V, target_s=15.0):
                       f"{el:.1f} s"}
 
 
-def main():
-    ap = argparse.ArgumentParser()
-    ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=2)
-    ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--workload", default="vgos-6bl-32x64-20000")
-    ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-seconds", type=float, default=15.0)
-    ap.add_argument("--precision", default="f32", choices=["f32", "f16x3", "f16"],
-                    help="f32: vector-ALU FFT transforms; f16x3: MBD on the matrix cores "
-                         "as three float16 products (float32-grade); f16: one float16 "
-                         "product with complex32 (float16) stored cross spectra")
-    ap.add_argument("--copy-calibration-mb", type=int, default=0,
-                    help="after the timed steps, run one plain device copy (float32 "
-                         "multiply by 1) of this many MiB, to calibrate HBM counters")
-    args = ap.parse_args()
-    if args.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU only: --gpus must be 1 "
-                                   "(the sharding design is described in DESIGN.md)"}))
-        sys.exit(2)
-
-    import numpy as np
+def run_form(args, wl, V, prec, dev):
+    """Time `args.steps` full searches in one precision form; returns the
+    JSON record (without the CPU baseline)."""
     import torch
     from paper_1801_02391_amd import frbx
     from paper_1801_02391_amd import workloads as W
-
-    wl = W.get_workload(args.workload, search=dict(precision=args.precision))
-    lay, srch = wl["layout"], wl["search"]
-    log(f"generating {args.workload}")
-    t0 = time.perf_counter()
-    V, truth = W.generate(wl)
-    log(f"generated {V.nbytes / 1e9:.2f} GB in {time.perf_counter() - t0:.1f} s")
-    dev = torch.device("cuda:0")
-    if args.precision == "f16":
+    lay = wl["layout"]
+    srch = dict(wl["search"], precision=prec)
+    if prec == "f16":
         Vt = torch.from_numpy(W.to_complex32(V)).to(dev)
     else:
         Vt = torch.from_numpy(V).to(dev)
-    del V
     torch.cuda.synchronize()
-
     s = frbx.Search(lay, device=0)
     s.configure(srch)
     s.load(Vt)
@@ -160,14 +133,14 @@ def main():
     cells_per_unit = R * PJ * M
     avg_ms = tim["fringe_ms"] / max(1, tim["n_fringe"])
     units_per_launch = tim["fringe_units"] / max(1, tim["n_fringe"])
-    if args.precision == "f32":
+    if prec == "f32":
         # FFT-form FP32 work on the vector ALUs
         fpc = fringe_flops_per_cell(N, J, P, M)
         bound, peak, kern = "alu", PEAK_FP32_TFLOPS, "fringe_kernel"
     else:
         # matrix-core work: the real-embedded MBD GEMM, 2 x (2N) x (2M) flops
         # per SBD bin, i.e. 8 N flops per cell per float16 product
-        fpc = 8 * N * (3 if args.precision == "f16x3" else 1)
+        fpc = 8 * N * (3 if prec == "f16x3" else 1)
         bound, peak, kern = "mfma", PEAK_FP16_MFMA_TFLOPS, "fringe_mfma_kernel"
     flops_launch = units_per_launch * cells_per_unit * fpc
     achieved = flops_launch / (avg_ms * 1e-3) / 1e12 if avg_ms > 0 else 0.0
@@ -195,8 +168,8 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": {"f32": "f32", "f16x3": "f32 (MBD as 3 x f16 MFMA)",
-                  "f16": "f16 storage + f16 MFMA, f32 accumulate"}[args.precision],
+        "dtype": {"f32": "f32", "f16x3": "f16x3 (MBD: 3 f16 MFMA products, f32 accumulate)",
+                  "f16": "f16 storage + f16 MFMA, f32 accumulate"}[prec],
         "data": "synthetic",
         "config": {"workload": args.workload, "baselines": B, "if": N, "chan": J,
                    "frames": lay["n_frames"], "dm_trials": D, "rate_bins": R, "sbd_bins": PJ,
@@ -207,10 +180,65 @@ def main():
         "detections": n_det,
         "reported_groups": n_rep,
     }
+    del s, Vt
+    torch.cuda.empty_cache()
+    return out
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=2)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--workload", default="vgos-6bl-32x64-20000")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--precision", default="f32", choices=["f32", "f16x3", "f16"],
+                    help="f32: vector-ALU FFT transforms; f16x3: MBD on the matrix cores "
+                         "as three float16 products (float32-grade); f16: one float16 "
+                         "product with complex32 (float16) stored cross spectra")
+    ap.add_argument("--only", action="store_true",
+                    help="time only --precision (default: also the other forms, reported "
+                         "with their speedup over it)")
+    ap.add_argument("--copy-calibration-mb", type=int, default=0,
+                    help="after the timed steps, run one plain device copy (float32 "
+                         "multiply by 1) of this many MiB, to calibrate HBM counters")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(json.dumps({"error": "this build runs on one GPU only: --gpus must be 1 "
+                                   "(the sharding design is described in DESIGN.md)"}))
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+    from paper_1801_02391_amd import frbx
+    from paper_1801_02391_amd import workloads as W
+
+    wl = W.get_workload(args.workload)
+    lay, srch = wl["layout"], wl["search"]
+    log(f"generating {args.workload}")
+    t0 = time.perf_counter()
+    V, truth = W.generate(wl)
+    log(f"generated {V.nbytes / 1e9:.2f} GB in {time.perf_counter() - t0:.1f} s")
+    dev = torch.device("cuda:0")
+    torch.cuda.synchronize()
+
+    forms = [args.precision] if args.only else [args.precision] + [p for p in ("f16x3", "f16")
+                                                                   if p != args.precision]
+    results = {}
+    for prec in forms:
+        results[prec] = run_form(args, wl, V, prec, dev)
+    out = results[args.precision]
+    if len(forms) > 1:
+        base = out["value"]
+        out["precision_forms"] = {
+            p: {"value": r["value"], "ms_per_step": r["ms_per_step"], "dtype": r["dtype"],
+                "speedup_vs_" + args.precision: r["value"] / base, "roofline": r["roofline"],
+                "detections": r["detections"], "reported_groups": r["reported_groups"]}
+            for p, r in results.items() if p != args.precision}
     if not args.no_cpu_baseline:
         log("timing the oracle on a CPU sample")
-        Vs, _ = W.generate(wl, baselines=[0])
-        out["cpu_baseline"] = cpu_baseline(wl, Vs, args.cpu_seconds)
+        out["cpu_baseline"] = cpu_baseline(wl, V[:1], args.cpu_seconds)
     print(json.dumps(out), flush=True)
 
 
