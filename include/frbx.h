@@ -227,6 +227,29 @@ frbx_status frbx_get_candidates(const frbx_ctx *ctx, frbx_candidate *out, int64_
  * N_bl,min), in creation order. */
 frbx_status frbx_get_groups(const frbx_ctx *ctx, frbx_group *out, int64_t cap, int64_t *n);
 
+/* Multiple-baselines power summation scheme (Sec. 2.4.2), after frbx_run:
+ * the powers of corresponding segments of the listed baselines are summed,
+ * normalised per (DM trial, window) with Eq. 6, thresholded, and filtered
+ * with steps b and d of Sec. 2.4.1 (step c is skipped: MBD has no meaning
+ * for the combined baseline); then the best DM bin per pulse (Sec. 5.3).
+ * baselines: host array of n_bl distinct indices.  Detections are written as
+ * for frbx_get_candidates with baseline = -1 and the summed power in
+ * `power`. */
+frbx_status frbx_power_sum(frbx_ctx *ctx, const int32_t *baselines, int32_t n_bl,
+                           frbx_candidate *out, int64_t cap, int64_t *n);
+
+/* Initial-phase and channel-delay extraction of Appendix A on a calibrator
+ * segment: APs [k0, k0 + len) of `baseline` summed without dedispersion or
+ * calibration; the (SBD, MBD) cell of maximum |G| on the current delay
+ * grids; per IF the channel delay tau0 maximising the amplitude of
+ * sum_{j>=1} S(n,j) exp(-2 pi i f_j SBD) exp(-2 pi i (f_j - f_bw/2) tau)
+ * (|tau| <= 1/(2 chan_bw), refined to ~1e-9 us) and the initial phase
+ * phi0 = angle of sum_{j>=1} S(n,j) exp(-2 pi i [f_j SBD + (f0^n -
+ * f_ref,fit) MBD + (f_j - f_bw/2) tau0]).  tau0_us, phi0_rad: host [N]
+ * outputs, ready for frbx_set_calibration (row `baseline`). */
+frbx_status frbx_calibrate(frbx_ctx *ctx, int32_t baseline, int64_t k0, int32_t len,
+                           double *tau0_us, double *phi0_rad);
+
 /* |G|^2 of every cell of one segment, [R][PJ][M] float32 into a device
  * buffer of the caller (for element-wise checks of the fringe transform;
  * needs a loaded context with valid grids). */

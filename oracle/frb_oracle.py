@@ -22,6 +22,7 @@ Steps and the passages they follow (section / equation of the paper):
   O12 best DM bin per detection ................... Sec. 5.3 (coarse search)
   O13 cross-baseline matching ..................... Sec. 2.4.1 (cross matching)
   PS  power-summation scheme ...................... Sec. 2.4.2
+  CA  initial-phase / channel-delay extraction ..... Appendix A
   H1  DM resolution ............................... Eq. 10
   H2  noise level ................................. Eq. 7
 
@@ -480,6 +481,73 @@ def power_sum_detect(cube_rows, segs, t_amb, threshold, n_win_min):
             cands.append(dict(wi=wi, l=l, q=int(q), k0=int(q) * h, p_norm=float(pn[q]),
                               power=float(tot[q]), mbd_us=0.0))
     return [det for det, _ in group_windows(cands, t_amb, n_win_min, use_mbd=False)]
+
+
+def power_sum_search(cube_P, segs, t_amb, threshold, n_win_min, baselines):
+    """PS over DM trials: cube_P[b][d][seg] (window-major segments).  For
+    every DM trial, the Sec. 2.4.2 steps on the summed power of the listed
+    baselines; then the best DM bin per pulse (Sec. 5.3).  Returns the
+    detections (dicts with d, wi, l, q, k0, power, p_norm, n_windows)."""
+    cube_P = np.asarray(cube_P, dtype=np.float64)
+    off = np.cumsum([0] + [q for (_, _, q) in segs])
+    dets = []
+    for d in range(cube_P.shape[1]):
+        rows = [[cube_P[b, d, off[wi]:off[wi + 1]] for b in baselines] for wi in range(len(segs))]
+        for det in power_sum_detect(rows, segs, t_amb, threshold, n_win_min):
+            det["d"] = d
+            dets.append(det)
+    return merge_dm(dets)
+
+
+def calibrate(Y, f0, chan_bw, e_sbd, e_mbd, tau_s, tau_m, f_ref, n_fine=64):
+    """CA, Appendix A on one calibrator segment Y[N][J] (the window sum,
+    j = 0 unused), starting from zero calibration (step a):
+      * the (SBD, MBD) cell maximising |G| of Eq. 5;
+      * channel delay of IF n: the delay tau maximising
+        |sum_{j>=1} Y(n,j) exp(-2 pi i f_j SBD) exp(-2 pi i (f_j - f_bw/2) tau)|
+        (the fit of Y exp(-2 pi i f_j SBD) of step c), on a grid n_fine times
+        finer than 1/(J chan_bw) over +-1/(2 chan_bw), refined by
+        golden-section search;
+      * initial phase of IF n: the angle of
+        sum_{j>=1} Y(n,j) exp(-2 pi i [f_j SBD + (f0^n - f_ref) MBD
+                                       + (f_j - f_bw/2) tau0^n]),
+        i.e. step c's formula taken after the channel delay is removed (the
+        reading that keeps the pair consistent with the Eq. 5 rotation; it
+        equals the printed order when channel delays are small).
+    Returns (tau0_us[N], phi0_rad[N], sbd_us, mbd_us)."""
+    Y = np.array(Y, dtype=np.complex128)
+    Y[:, 0] = 0.0
+    N, J = Y.shape
+    G = np.abs((Y @ e_sbd).T @ e_mbd)                       # [PJ][M]
+    s, m = np.unravel_index(int(np.argmax(G)), G.shape)
+    sbd, mbd = float(tau_s[s]), float(tau_m[m])
+    fj = np.arange(J, dtype=np.float64) * chan_bw
+    fbw = J * chan_bw
+    f0 = np.asarray(f0, dtype=np.float64)
+    Z = Y * np.exp(-2j * np.pi * fj * sbd)[None, :]
+    grid = np.linspace(-0.5 / chan_bw, 0.5 / chan_bw, n_fine * J + 1)
+    tau0 = np.zeros(N)
+
+    def amp(n, t):
+        return abs((Z[n] * np.exp(-2j * np.pi * (fj - fbw / 2) * t)).sum())
+
+    for n in range(N):
+        vals = np.abs(Z[n][None, :] @ np.exp(-2j * np.pi * (fj[:, None] - fbw / 2) * grid[None, :]))[0]
+        i = int(np.argmax(vals))
+        a, b = grid[max(i - 1, 0)], grid[min(i + 1, len(grid) - 1)]
+        gr = (math.sqrt(5) - 1) / 2
+        c, d = b - gr * (b - a), a + gr * (b - a)
+        for _ in range(80):
+            if amp(n, c) > amp(n, d):
+                b = d
+            else:
+                a = c
+            c, d = b - gr * (b - a), a + gr * (b - a)
+        tau0[n] = 0.5 * (a + b)
+    rot = np.exp(-2j * np.pi * (fj[None, :] * sbd + (f0 - f_ref)[:, None] * mbd
+                                + (fj[None, :] - fbw / 2) * tau0[:, None]))
+    phi0 = np.angle((Y * rot).sum(axis=1))
+    return tau0, phi0, sbd, mbd
 
 
 # ----------------------------------------------------------------------------

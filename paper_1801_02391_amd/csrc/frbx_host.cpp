@@ -7,6 +7,7 @@
 
 #include <algorithm>
 #include <cmath>
+#include <complex>
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
@@ -68,6 +69,7 @@ struct frbx_ctx {
   std::vector<int32_t> mbd_row;
   std::vector<int64_t> q_if;  // MBD lattice position of each IF
   std::vector<int> rate_off;
+  int dd_group = 1;          // DM trials per staged dedispersion tile
 
   // device memory
   const void *d_vis = nullptr;
@@ -247,6 +249,21 @@ frbx_status prepare(frbx_ctx *c) {
   if (mn < 0) return c->fail(FRBX_E_INVAL, "negative AP offset (negative DM trial?)");
   c->dk_max = mx;
   c->k_eff = c->K - mx;
+  // largest group of consecutive DM trials whose offsets differ by less than
+  // the staged spread for every channel
+  {
+    int g = 1;
+    auto fits = [&](int gs) {
+      for (int d0 = 0; d0 + gs - 1 < D; d0 += 1) {
+        const int32_t *a0 = c->dk.data() + size_t(d0) * NJ, *a1 = c->dk.data() + size_t(d0 + gs - 1) * NJ;
+        for (int i = 0; i < NJ; ++i)
+          if (a1[i] - a0[i] >= frbx::kDedispSpread || a1[i] < a0[i]) return false;
+      }
+      return true;
+    };
+    while (g < D && g < 64 && fits(g + 1)) ++g;
+    c->dd_group = g;
+  }
   const int nw = int(c->windows.size());
   c->hop.assign(nw, 0);
   c->nseg.assign(nw, 0);
@@ -798,6 +815,7 @@ frbx_status frbx_run(frbx_ctx *c) {
         da.out = c->d_w;
         da.k_eff = c->k_eff;
         da.nj = NJ;
+        da.group = c->dd_group;
         int sp = c->span_begin(1, int64_t(ndt) * c->k_eff);
         if ((s = c->hip(frbx::launch_dedisperse(da, c->stream), "dedisperse launch")) != FRBX_OK) return s;
         c->span_end(sp);
@@ -1022,6 +1040,7 @@ frbx_status frbx_dump_segment(frbx_ctx *c, int32_t b, int32_t d, int32_t w, int6
   da.out = c->d_w;
   da.k_eff = c->k_eff;
   da.nj = NJ;
+  da.group = 1;
   if ((s = c->hip(frbx::launch_dedisperse(da, c->stream), "dedisperse launch")) != FRBX_OK) return s;
   frbx::FringeArgs fa{};
   fa.w = c->d_w;
@@ -1060,6 +1079,195 @@ frbx_status frbx_dump_segment(frbx_ctx *c, int32_t b, int32_t d, int32_t w, int6
   }
   if ((s = c->hip(le, "fringe launch")) != FRBX_OK) return s;
   return c->hip(hipStreamSynchronize(c->stream), "dump");
+}
+
+frbx_status frbx_power_sum(frbx_ctx *c, const int32_t *bl, int32_t n_bl, frbx_candidate *out, int64_t cap,
+                           int64_t *n) {
+  if (!c) return FRBX_E_INVAL;
+  if (!c->have) return c->fail(FRBX_E_STATE, "frbx_power_sum before frbx_run");
+  if (!bl || n_bl < 1 || n_bl > c->B) return c->fail(FRBX_E_INVAL, "need 1..B baselines");
+  for (int i = 0; i < n_bl; ++i) {
+    if (bl[i] < 0 || bl[i] >= c->B) return c->fail(FRBX_E_INVAL, "baseline index out of range");
+    for (int k = 0; k < i; ++k)
+      if (bl[k] == bl[i]) return c->fail(FRBX_E_INVAL, "baselines must be distinct");
+  }
+  if (hipSetDevice(c->device) != hipSuccess) return c->fail(FRBX_E_DEVICE, "hipSetDevice failed");
+  const int D = c->n_dm, nw = int(c->windows.size());
+  const int64_t S = c->seg_total, len = int64_t(D) * S;
+  const int rows = D * nw;
+  std::vector<frbx_candidate> cross;
+  if (S > 0) {
+    float *d_sum = nullptr;
+    int32_t *d_bl = nullptr;
+    double *d_m = nullptr, *d_s = nullptr;
+    int64_t *d_c = nullptr;
+    auto cleanup = [&]() { dfree(d_sum); dfree(d_bl); dfree(d_m); dfree(d_s); dfree(d_c); };
+    if (hipMalloc(reinterpret_cast<void **>(&d_sum), size_t(len) * sizeof(float)) != hipSuccess ||
+        hipMalloc(reinterpret_cast<void **>(&d_bl), size_t(n_bl) * sizeof(int32_t)) != hipSuccess ||
+        hipMalloc(reinterpret_cast<void **>(&d_m), size_t(rows) * sizeof(double)) != hipSuccess ||
+        hipMalloc(reinterpret_cast<void **>(&d_s), size_t(rows) * sizeof(double)) != hipSuccess ||
+        hipMalloc(reinterpret_cast<void **>(&d_c), size_t(rows) * sizeof(int64_t)) != hipSuccess) {
+      cleanup();
+      return c->fail(FRBX_E_NOMEM, "device allocation failed");
+    }
+    frbx_status s = c->hip(hipMemcpy(d_bl, bl, size_t(n_bl) * sizeof(int32_t), hipMemcpyHostToDevice), "copy");
+    if (s == FRBX_OK) s = c->hip(frbx::launch_cube_sum(c->d_power, len, d_bl, n_bl, d_sum, len, c->stream), "sum launch");
+    frbx::StatsArgs st{};
+    st.power = d_sum;
+    st.pidx = c->d_pidx;
+    st.seg_total = int(S);
+    st.n_win = nw;
+    for (int w = 0; w < nw; ++w) {
+      st.win_off[w] = c->segoff[w];
+      st.win_q[w] = c->nseg[w];
+    }
+    st.threshold = c->threshold;
+    st.mean = d_m;
+    st.stdev = d_s;
+    st.count = d_c;
+    st.out = c->d_cross;
+    st.n_out = c->d_ncross;
+    st.cap = c->cross_cap;
+    unsigned long long ncr = 0;
+    for (int attempt = 0; attempt < 2 && s == FRBX_OK; ++attempt) {
+      s = c->hip(hipMemsetAsync(c->d_ncross, 0, sizeof(unsigned long long), c->stream), "memset");
+      if (s == FRBX_OK) s = c->hip(frbx::launch_stats(st, rows, c->stream), "stats launch");
+      if (s == FRBX_OK)
+        s = c->hip(hipMemcpyAsync(&ncr, c->d_ncross, sizeof(ncr), hipMemcpyDeviceToHost, c->stream), "count");
+      if (s == FRBX_OK) s = c->hip(hipStreamSynchronize(c->stream), "power sum");
+      if (s != FRBX_OK || int64_t(ncr) <= c->cross_cap) break;
+      dfree(c->d_cross);
+      c->cross_cap = 0;
+      if (hipMalloc(reinterpret_cast<void **>(&c->d_cross), size_t(ncr) * sizeof(DevCrossing)) != hipSuccess) {
+        cleanup();
+        return c->fail(FRBX_E_NOMEM, "device allocation for crossings failed");
+      }
+      c->cross_cap = int64_t(ncr);
+      st.out = c->d_cross;
+      st.cap = c->cross_cap;
+    }
+    std::vector<DevCrossing> hc(ncr);
+    if (s == FRBX_OK && ncr)
+      s = c->hip(hipMemcpy(hc.data(), c->d_cross, ncr * sizeof(DevCrossing), hipMemcpyDeviceToHost), "copy");
+    cleanup();
+    if (s != FRBX_OK) return s;
+    std::sort(hc.begin(), hc.end(), [](const DevCrossing &x, const DevCrossing &y) {
+      return x.row != y.row ? x.row < y.row : x.q < y.q;
+    });
+    for (const DevCrossing &x : hc) {
+      frbx_candidate k{};
+      const int w = x.row % nw;
+      k.baseline = -1;
+      k.dm_index = x.row / nw;
+      k.window_index = w;
+      k.window_len = c->windows[w];
+      k.segment = x.q;
+      k.k0 = int64_t(x.q) * c->hop[w];
+      k.dm = c->dm_lo + k.dm_index * c->dm_step;
+      k.power = x.power;
+      k.power_norm = x.pnorm;
+      k.rate_idx = k.sbd_idx = k.mbd_idx = -1;
+      k.group_id = -1;
+      cross.push_back(k);
+    }
+  }
+  std::vector<frbx_candidate> dets;
+  std::vector<frbx_group> groups;
+  detect_impl(cross.data(), int64_t(cross.size()), c->t_amb, c->n_win_min, 1, false, dets, groups);
+  for (auto &d : dets) d.group_id = -1;
+  return copy_out(dets, out, cap, n);
+}
+
+frbx_status frbx_calibrate(frbx_ctx *c, int32_t b, int64_t k0, int32_t len, double *tau0, double *phi0) {
+  if (!c) return FRBX_E_INVAL;
+  if (!c->loaded) return c->fail(FRBX_E_STATE, "frbx_calibrate before frbx_load");
+  if (b < 0 || b >= c->B || len < 1 || k0 < 0 || k0 + len > c->K || !tau0 || !phi0)
+    return c->fail(FRBX_E_INVAL, "calibrator segment out of range");
+  if (hipSetDevice(c->device) != hipSuccess) return c->fail(FRBX_E_DEVICE, "hipSetDevice failed");
+  frbx_status s = prepare(c);
+  if (s != FRBX_OK) return s;
+  const int N = c->N, J = c->J, NJ = N * J;
+  float2 *d_y = nullptr;
+  if (hipMalloc(reinterpret_cast<void **>(&d_y), size_t(NJ) * sizeof(float2)) != hipSuccess)
+    return c->fail(FRBX_E_NOMEM, "device allocation failed");
+  const void *vb = static_cast<const char *>(c->d_vis) + size_t(b) * NJ * size_t(c->K) * (c->vis_f16 ? 4 : 8);
+  std::vector<float2> hy(NJ);
+  s = c->hip(frbx::launch_segment_sum(vb, c->vis_f16, c->K, NJ, k0, len, d_y, c->stream), "segment sum");
+  if (s == FRBX_OK) s = c->hip(hipStreamSynchronize(c->stream), "segment sum");
+  if (s == FRBX_OK) s = c->hip(hipMemcpy(hy.data(), d_y, size_t(NJ) * sizeof(float2), hipMemcpyDeviceToHost), "copy");
+  dfree(d_y);
+  if (s != FRBX_OK) return s;
+  using cd = std::complex<double>;
+  auto cis = [](double cycles) {  // exp(-2 pi i cycles), reduced first
+    const double r = cycles - std::nearbyint(cycles);
+    return cd(std::cos(kTwoPi * r), -std::sin(kTwoPi * r));
+  };
+  std::vector<cd> Y(NJ);
+  for (int i = 0; i < NJ; ++i) Y[i] = (i % J == 0) ? cd(0, 0) : cd(hy[i].x, hy[i].y);
+  // (SBD, MBD) cell of maximum |G| (Eq. 5) on the current grids
+  const int PJ = c->sbd_pad * J, M = c->n_mbd;
+  const double df = c->df, fbw = J * df;
+  const double fref = std::isnan(c->f_ref_fit) ? c->f0[0] : c->f_ref_fit;
+  std::vector<cd> X(size_t(N) * PJ);
+  for (int n = 0; n < N; ++n)
+    for (int sb = 0; sb < PJ; ++sb) {
+      cd acc(0, 0);
+      for (int j = 1; j < J; ++j)
+        acc += Y[size_t(n) * J + j] * cis(double((int64_t(j) * (sb - PJ / 2)) % PJ) / PJ);
+      X[size_t(n) * PJ + sb] = acc;
+    }
+  double best = -1.0;
+  int bs = 0, bm = 0;
+  std::vector<cd> em(size_t(N) * M);
+  for (int n = 0; n < N; ++n)
+    for (int m = 0; m < M; ++m) em[size_t(n) * M + m] = cis((c->f0[n] - fref) * (m - M / 2) * c->mbd_step);
+  for (int sb = 0; sb < PJ; ++sb)
+    for (int m = 0; m < M; ++m) {
+      cd acc(0, 0);
+      for (int n = 0; n < N; ++n) acc += X[size_t(n) * PJ + sb] * em[size_t(n) * M + m];
+      const double a = std::abs(acc);
+      if (a > best) best = a, bs = sb, bm = m;
+    }
+  const double sbd = (bs - PJ / 2.0) / (PJ * df), mbd = (bm - M / 2.0) * c->mbd_step;
+  // channel delay per IF, then the initial phase of the delay-corrected sum
+  const int NG = 64 * J + 1;
+  for (int n = 0; n < N; ++n) {
+    std::vector<cd> Z(J);
+    for (int j = 0; j < J; ++j) Z[j] = Y[size_t(n) * J + j] * cis(j * df * sbd);
+    auto amp = [&](double t) {
+      const cd step = cis(df * t);
+      cd ph = cis(-fbw / 2.0 * t), acc(0, 0);  // exp(-2 pi i (f_j - f_bw/2) t), j = 0 first
+      for (int j = 0; j < J; ++j) {
+        acc += Z[j] * ph;
+        ph *= step;
+      }
+      return std::abs(acc);
+    };
+    const double lo = -0.5 / df, hi = 0.5 / df;
+    int bi = 0;
+    double bv = -1.0;
+    for (int g = 0; g < NG; ++g) {
+      const double a = amp(lo + (hi - lo) * g / (NG - 1));
+      if (a > bv) bv = a, bi = g;
+    }
+    double a = lo + (hi - lo) * std::max(bi - 1, 0) / (NG - 1);
+    double bb = lo + (hi - lo) * std::min(bi + 1, NG - 1) / (NG - 1);
+    const double gr = (std::sqrt(5.0) - 1.0) / 2.0;
+    double x1 = bb - gr * (bb - a), x2 = a + gr * (bb - a);
+    for (int it = 0; it < 80; ++it) {
+      if (amp(x1) > amp(x2)) bb = x2;
+      else a = x1;
+      x1 = bb - gr * (bb - a);
+      x2 = a + gr * (bb - a);
+    }
+    const double t0 = 0.5 * (a + bb);
+    cd acc(0, 0);
+    for (int j = 1; j < J; ++j)
+      acc += Y[size_t(n) * J + j] * cis(j * df * sbd + (c->f0[n] - fref) * mbd + (j * df - fbw / 2.0) * t0);
+    tau0[n] = t0;
+    phi0[n] = std::atan2(acc.imag(), acc.real());
+  }
+  return FRBX_OK;
 }
 
 frbx_status frbx_set_timing(frbx_ctx *c, int enable) {

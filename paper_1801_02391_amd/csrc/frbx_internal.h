@@ -33,7 +33,15 @@ struct DedisperseArgs {
   float2 *out;         // [n_dt][k_eff][NJ]
   int64_t k_eff;       // K - dk_max
   int32_t nj;          // N * J
+  int32_t group;       // DM trials sharing one staged input tile (>= 1); the
+                       // AP offsets of a group differ by < kDedispSpread
 };
+
+// Dedispersion tile: 32 channels x 128 APs, staged input span up to
+// 128 + kDedispSpread APs per channel.
+constexpr int kDedispCh = 32;
+constexpr int kDedispAp = 128;
+constexpr int kDedispSpread = 128;
 
 // Fringe search of every segment of one baseline and DM tile (Sec. 2.3,
 // Eq. 5 with the rate term of Eq. 4; Sec. 5.1): segment sums of W with rate
@@ -103,6 +111,15 @@ hipError_t launch_fringe_mfma(int n_chan, int n_if, int n_pass, const FringeArgs
                               size_t lds_bytes, int grid, hipStream_t s);
 size_t fringe_mfma_lds_bytes(int n_chan, int n_if, int sbd_pad, int n_pass);
 bool fringe_mfma_supported(int n_chan, int n_mbd, int n_if, int sbd_pad, int n_pass);
+
+// out[d][s] = sum over the listed baselines of power[b][d][s]
+hipError_t launch_cube_sum(const float *power, int64_t bl_stride, const int32_t *baselines,
+                           int n_bl, float *out, int64_t n, hipStream_t s);
+
+// Y[c] = sum_{k0 <= k < k0 + len} V[c][k] (complex64 or complex32 input),
+// c over n_chan_total channels of one baseline
+hipError_t launch_segment_sum(const void *vis, int in_f16, int64_t n_frames, int n_ch, int64_t k0,
+                              int len, float2 *out, hipStream_t s);
 
 // max(|re|, |im|) over n complex values (float32 or float16 pairs) into
 // *out (float bits, caller zeroes it first)

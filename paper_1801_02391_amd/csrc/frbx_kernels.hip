@@ -252,28 +252,53 @@ __device__ __forceinline__ float2 load_vis(const void *p, int64_t i, bool f16) {
   return static_cast<const float2 *>(p)[i];
 }
 
+// One work-group dedisperses a tile of 32 channels x 128 APs for a group of
+// DM trials: each channel's input span (the 128 APs shifted by the group's
+// smallest offset, plus the offset spread of the group) is read once,
+// coalesced, into LDS; every trial of the group then writes its 128
+// AP-major spectra from the staged span (32 channels = 256 contiguous bytes
+// per AP), with the Eq. 5 calibration applied on the way.
 template <bool F16>
 __global__ __launch_bounds__(kBlock) void dedisperse_kernel(DedisperseArgs a) {
-  __shared__ float2 tile[64][65];
-  const int64_t kt = int64_t(blockIdx.x) * 64;
-  const int ct = blockIdx.y * 64;
-  const int dl = blockIdx.z;
-  const int32_t *dkd = a.dk + int64_t(a.d0 + dl) * a.nj;
+  constexpr int SW = kDedispAp + kDedispSpread + 1;   // staged APs per channel (+1 pad)
+  __shared__ float2 tile[kDedispCh][SW];
+  __shared__ int32_t dks[kDedispCh];
+  const int64_t kt = int64_t(blockIdx.x) * kDedispAp;
+  const int ct = blockIdx.y * kDedispCh;
+  const int g0 = blockIdx.z * a.group;                  // first trial of the group (tile-local)
+  const int ng = min(a.group, a.n_dt - g0);
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-  for (int i = w; i < 64; i += 4) {
+  const int32_t *dk0 = a.dk + int64_t(a.d0 + g0) * a.nj;
+  const int32_t *dk1 = a.dk + int64_t(a.d0 + g0 + ng - 1) * a.nj;
+  if (threadIdx.x < kDedispCh) {
+    const int c = ct + threadIdx.x;
+    dks[threadIdx.x] = c < a.nj ? dk0[c] : 0;
+  }
+  // stage: wave w loads channels w, w + 4, ...; frames base .. base + span
+  for (int i = w; i < kDedispCh; i += kBlock / 64) {
     const int c = ct + i;
-    const int64_t k = kt + lane;
-    float2 v = make_float2(0.f, 0.f);
-    if (c < a.nj && k < a.k_eff) v = load_vis(a.vis, int64_t(c) * a.n_frames + k + dkd[c], F16);
-    tile[i][lane] = v;
+    if (c >= a.nj) continue;
+    const int64_t base = kt + dk0[c];
+    const int span = kDedispAp + (dk1[c] - dk0[c]);
+    const int64_t row = int64_t(c) * a.n_frames;
+    for (int x = lane; x < span; x += 64) {
+      const int64_t f = base + x;
+      tile[i][x] = f < a.n_frames ? load_vis(a.vis, row + f, F16) : make_float2(0.f, 0.f);
+    }
   }
   __syncthreads();
-  float2 *outd = a.out + int64_t(dl) * a.k_eff * a.nj;
-  const int c = ct + lane;
+  // write: lane -> channel (32 per half-wave), 8 APs per pass over the block
+  const int cl = lane & (kDedispCh - 1);
+  const int c = ct + cl;
   const float2 cal = c < a.nj ? a.cal[c] : make_float2(0.f, 0.f);
-  for (int i = w; i < 64; i += 4) {
-    const int64_t k = kt + i;
-    if (c < a.nj && k < a.k_eff) outd[k * a.nj + c] = cmul(tile[lane][i], cal);
+  const int kr = threadIdx.x / kDedispCh;                // 0..7
+  for (int j = 0; j < ng; ++j) {
+    const int shift = c < a.nj ? a.dk[int64_t(a.d0 + g0 + j) * a.nj + c] - dks[cl] : 0;
+    float2 *outd = a.out + int64_t(g0 + j) * a.k_eff * a.nj;
+    for (int kk = kr; kk < kDedispAp; kk += kBlock / kDedispCh) {
+      const int64_t k = kt + kk;
+      if (c < a.nj && k < a.k_eff) outd[k * a.nj + c] = cmul(tile[cl][kk + shift], cal);
+    }
   }
 }
 
@@ -745,6 +770,33 @@ __global__ __launch_bounds__(kBlock) void fringe_mfma_kernel(FringeArgs a) {
   }
 }
 
+__global__ __launch_bounds__(kBlock) void cube_sum_kernel(const float *power, int64_t bl_stride,
+                                                          const int32_t *bl, int n_bl, float *out,
+                                                          int64_t n) {
+  for (int64_t i = int64_t(blockIdx.x) * kBlock + threadIdx.x; i < n;
+       i += int64_t(gridDim.x) * kBlock) {
+    float acc = 0.f;
+    for (int b = 0; b < n_bl; ++b) acc += power[int64_t(bl[b]) * bl_stride + i];
+    out[i] = acc;
+  }
+}
+
+// one wave per channel: lanes stride the APs, then a wave reduction
+__global__ __launch_bounds__(kBlock) void segment_sum_kernel(const void *vis, int in_f16,
+                                                             int64_t n_frames, int n_ch, int64_t k0,
+                                                             int len, float2 *out) {
+  const int c = blockIdx.x * (kBlock / 64) + (threadIdx.x >> 6);
+  const int lane = threadIdx.x & 63;
+  if (c >= n_ch) return;
+  float2 acc = make_float2(0.f, 0.f);
+  for (int u = lane; u < len; u += 64) acc = cadd(acc, load_vis(vis, int64_t(c) * n_frames + k0 + u, in_f16 != 0));
+  for (int off = 32; off > 0; off >>= 1) {
+    acc.x += __shfl_xor(acc.x, off, 64);
+    acc.y += __shfl_xor(acc.y, off, 64);
+  }
+  if (lane == 0) out[c] = acc;
+}
+
 __global__ __launch_bounds__(kBlock) void absmax_kernel(const void *vis, int64_t n, int in_f16,
                                                         unsigned int *out) {
   float m = 0.f;
@@ -762,7 +814,9 @@ __global__ __launch_bounds__(kBlock) void absmax_kernel(const void *vis, int64_t
 // ---------------------------------------------------------------- launchers
 hipError_t launch_dedisperse(const DedisperseArgs &a, hipStream_t s) {
   (void)hipGetLastError();
-  dim3 grid(unsigned((a.k_eff + 63) / 64), unsigned((a.nj + 63) / 64), unsigned(a.n_dt));
+  if (a.group < 1) return hipErrorInvalidValue;
+  dim3 grid(unsigned((a.k_eff + kDedispAp - 1) / kDedispAp), unsigned((a.nj + kDedispCh - 1) / kDedispCh),
+            unsigned((a.n_dt + a.group - 1) / a.group));
   if (a.in_f16)
     hipLaunchKernelGGL(dedisperse_kernel<true>, grid, dim3(kBlock), 0, s, a);
   else
@@ -932,6 +986,25 @@ bool fringe_mfma_supported(int n_chan, int n_mbd, int n_if, int sbd_pad, int n_p
   if (n_if * JB > kBlock) return false;
   const size_t b = fringe_mfma_lds_bytes(n_chan, n_if, sbd_pad, n_pass);
   return b > 0 && b <= 150 * 1024;
+}
+
+hipError_t launch_cube_sum(const float *power, int64_t bl_stride, const int32_t *baselines, int n_bl,
+                           float *out, int64_t n, hipStream_t s) {
+  (void)hipGetLastError();
+  const int64_t blocks = std::min<int64_t>(8192, (n + kBlock - 1) / kBlock);
+  if (blocks <= 0) return hipSuccess;
+  hipLaunchKernelGGL(cube_sum_kernel, dim3(unsigned(blocks)), dim3(kBlock), 0, s, power, bl_stride,
+                     baselines, n_bl, out, n);
+  return hipGetLastError();
+}
+
+hipError_t launch_segment_sum(const void *vis, int in_f16, int64_t n_frames, int n_ch, int64_t k0, int len,
+                              float2 *out, hipStream_t s) {
+  (void)hipGetLastError();
+  const int blocks = (n_ch + kBlock / 64 - 1) / (kBlock / 64);
+  hipLaunchKernelGGL(segment_sum_kernel, dim3(blocks), dim3(kBlock), 0, s, vis, in_f16, n_frames, n_ch,
+                     k0, len, out);
+  return hipGetLastError();
 }
 
 hipError_t launch_absmax(const void *vis, int64_t n, int in_f16, unsigned int *out, hipStream_t s) {

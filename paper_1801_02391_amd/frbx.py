@@ -81,6 +81,8 @@ _SIGS = {
     "frbx_get_groups": ([_P, _P, C.c_int64, _P], C.c_int),
     "frbx_dump_segment": ([_P, C.c_int32, C.c_int32, C.c_int32, C.c_int64, _P], C.c_int),
     "frbx_set_timing": ([_P, C.c_int], C.c_int),
+    "frbx_power_sum": ([_P, _P, C.c_int32, _P, C.c_int64, _P], C.c_int),
+    "frbx_calibrate": ([_P, C.c_int32, C.c_int64, C.c_int32, _P, _P], C.c_int),
     "frbx_get_timing": ([_P, _P], C.c_int),
     "frbx_ap_offsets": ([C.POINTER(Layout), C.c_double, C.c_double, C.c_int32, C.c_double, _P],
                         C.c_int),
@@ -325,6 +327,28 @@ class Search:
         arr = (Group * max(1, n.value))()
         self._chk(L.frbx_get_groups(self._h, arr, n.value, C.byref(n)), "get_groups")
         return [{f: getattr(arr[i], f) for f, _ in Group._fields_} for i in range(n.value)]
+
+    def power_sum(self, baselines):
+        """Sec. 2.4.2 detections from the summed power of `baselines`."""
+        bl = np.ascontiguousarray(baselines, dtype=np.int32)
+        L = lib()
+        n = C.c_int64(0)
+        s = L.frbx_power_sum(self._h, _ptr(bl), len(bl), None, 0, C.byref(n))
+        if s not in (OK, E_RANGE):
+            self._chk(s, "power_sum")
+        arr = (Candidate * max(1, n.value))()
+        self._chk(L.frbx_power_sum(self._h, _ptr(bl), len(bl), arr, n.value, C.byref(n)),
+                  "power_sum")
+        return records_to_dicts(arr[:n.value])
+
+    def calibrate(self, baseline, k0, length):
+        """Appendix A extraction on a calibrator segment -> (tau0_us[N], phi0_rad[N])."""
+        N = len(self._f0)
+        t = np.zeros(N)
+        p = np.zeros(N)
+        self._chk(lib().frbx_calibrate(self._h, int(baseline), int(k0), int(length), _ptr(t), _ptr(p)),
+                  "calibrate")
+        return t, p
 
     def set_timing(self, enable=True):
         self._chk(lib().frbx_set_timing(self._h, int(bool(enable))), "set_timing")
