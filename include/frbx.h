@@ -270,6 +270,10 @@ typedef struct {
   int64_t dedisperse_units;
   double stats_ms;
   int64_t n_stats;
+  int64_t dedisperse_bytes;   /* algorithmic bytes of the dedispersion
+                                 launches: every dedispersed spectrum written
+                                 once, every channel's input span read once
+                                 per group of DM trials */
 } frbx_timing;
 
 frbx_status frbx_set_timing(frbx_ctx *ctx, int enable);

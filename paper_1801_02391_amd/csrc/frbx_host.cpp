@@ -101,7 +101,7 @@ struct frbx_ctx {
   bool timing = false;
   std::vector<hipEvent_t> ev_pool;
   size_t ev_used = 0;
-  struct Span { int kind; int64_t units; hipEvent_t a, b; };
+  struct Span { int kind; int64_t units; hipEvent_t a, b; int64_t bytes; };
   std::vector<Span> spans;
   frbx_timing last_timing{};
 
@@ -135,7 +135,7 @@ struct frbx_ctx {
     hipEvent_t a = event(), b = event();
     if (!a || !b) return -1;
     hipEventRecord(a, stream);
-    spans.push_back(Span{kind, units, a, b});
+    spans.push_back(Span{kind, units, a, b, 0});
     return int(spans.size()) - 1;
   }
   void span_end(int i) {
@@ -147,7 +147,8 @@ struct frbx_ctx {
       float ms = 0.f;
       if (hipEventElapsedTime(&ms, sp.a, sp.b) != hipSuccess) continue;
       if (sp.kind == 0) t.fringe_ms += ms, t.n_fringe++, t.fringe_units += sp.units;
-      if (sp.kind == 1) t.dedisperse_ms += ms, t.n_dedisperse++, t.dedisperse_units += sp.units;
+      if (sp.kind == 1)
+        t.dedisperse_ms += ms, t.n_dedisperse++, t.dedisperse_units += sp.units, t.dedisperse_bytes += sp.bytes;
       if (sp.kind == 2) t.stats_ms += ms, t.n_stats++;
     }
     last_timing = t;
@@ -817,6 +818,18 @@ frbx_status frbx_run(frbx_ctx *c) {
         da.nj = NJ;
         da.group = c->dd_group;
         int sp = c->span_begin(1, int64_t(ndt) * c->k_eff);
+        if (sp >= 0) {
+          // writes: ndt x k_eff spectra; reads: each channel's span of
+          // k_eff + (offset spread of the group) APs once per group
+          int64_t bytes = int64_t(ndt) * c->k_eff * NJ * 8;
+          const int in_b = c->vis_f16 ? 4 : 8;
+          for (int g0 = 0; g0 < ndt; g0 += c->dd_group) {
+            const int g1 = std::min(ndt, g0 + c->dd_group) - 1;
+            const int32_t *a0 = c->dk.data() + size_t(d0 + g0) * NJ, *a1 = c->dk.data() + size_t(d0 + g1) * NJ;
+            for (int i = 0; i < NJ; ++i) bytes += (c->k_eff + (a1[i] - a0[i])) * in_b;
+          }
+          c->spans[sp].bytes = bytes;
+        }
         if ((s = c->hip(frbx::launch_dedisperse(da, c->stream), "dedisperse launch")) != FRBX_OK) return s;
         c->span_end(sp);
         frbx::FringeArgs fa{};

@@ -37,10 +37,11 @@ struct DedisperseArgs {
                        // AP offsets of a group differ by < kDedispSpread
 };
 
-// Dedispersion tile: 32 channels x 128 APs, staged input span up to
-// 128 + kDedispSpread APs per channel.
-constexpr int kDedispCh = 32;
-constexpr int kDedispAp = 128;
+// Dedispersion tile: 16 channels x 256 APs, staged input span up to
+// 256 + kDedispSpread APs per channel (the fastest of the tile shapes
+// measured on MI355X).
+constexpr int kDedispCh = 16;
+constexpr int kDedispAp = 256;
 constexpr int kDedispSpread = 128;
 
 // Fringe search of every segment of one baseline and DM tile (Sec. 2.3,

@@ -252,11 +252,11 @@ __device__ __forceinline__ float2 load_vis(const void *p, int64_t i, bool f16) {
   return static_cast<const float2 *>(p)[i];
 }
 
-// One work-group dedisperses a tile of 32 channels x 128 APs for a group of
+// One work-group dedisperses a tile of 16 channels x 256 APs for a group of
 // DM trials: each channel's input span (the 128 APs shifted by the group's
 // smallest offset, plus the offset spread of the group) is read once,
 // coalesced, into LDS; every trial of the group then writes its 128
-// AP-major spectra from the staged span (32 channels = 256 contiguous bytes
+// AP-major spectra from the staged span (16 channels = 128 contiguous bytes
 // per AP), with the Eq. 5 calibration applied on the way.
 template <bool F16>
 __global__ __launch_bounds__(kBlock) void dedisperse_kernel(DedisperseArgs a) {
@@ -287,7 +287,7 @@ __global__ __launch_bounds__(kBlock) void dedisperse_kernel(DedisperseArgs a) {
     }
   }
   __syncthreads();
-  // write: lane -> channel (32 per half-wave), 8 APs per pass over the block
+  // write: lane -> channel (kDedispCh consecutive lanes per AP)
   const int cl = lane & (kDedispCh - 1);
   const int c = ct + cl;
   const float2 cal = c < a.nj ? a.cal[c] : make_float2(0.f, 0.f);

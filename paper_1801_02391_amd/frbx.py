@@ -50,7 +50,8 @@ class Group(C.Structure):
 class Timing(C.Structure):
     _fields_ = [("fringe_ms", C.c_double), ("n_fringe", C.c_int64), ("fringe_units", C.c_int64),
                 ("dedisperse_ms", C.c_double), ("n_dedisperse", C.c_int64),
-                ("dedisperse_units", C.c_int64), ("stats_ms", C.c_double), ("n_stats", C.c_int64)]
+                ("dedisperse_units", C.c_int64), ("stats_ms", C.c_double), ("n_stats", C.c_int64),
+                ("dedisperse_bytes", C.c_int64)]
 
 
 CANDIDATE_FIELDS = [f for f, _ in Candidate._fields_ if f != "reserved"]
