@@ -227,6 +227,41 @@ frbx_status frbx_get_candidates(const frbx_ctx *ctx, frbx_candidate *out, int64_
  * N_bl,min), in creation order. */
 frbx_status frbx_get_groups(const frbx_ctx *ctx, frbx_group *out, int64_t cap, int64_t *n);
 
+/* ---- Streaming (chunked) search ------------------------------------------
+ * The search of a long observation in chunks of chunk_frames APs.  The
+ * library keeps, per baseline and channel, the last dk_max + l_max - 1 APs
+ * of the data seen so far (the DM-overlap carry) so that every segment of
+ * every window and DM trial is searched exactly once, by the first push that
+ * completes it; segment q of window l covers APs [q hop, q hop + l - 1] on the
+ * global AP axis, as in frbx_run.  The grids must be set before
+ * frbx_stream_begin and not changed until the next begin.
+ * After each push the per-push results are read with the usual getters:
+ * frbx_get_power_cube (the segments completed by this push, [B][D][S_push],
+ * windows in order), frbx_get_stats (Eq. 6 over this push's segments of each
+ * window: the statistics are per chunk), frbx_get_crossings (this push's
+ * crossings, global segment index and k0); frbx_get_candidates and
+ * frbx_get_groups cover all pushes since frbx_stream_begin. */
+typedef enum {
+  FRBX_IN_C64 = 0,   /* complex64 */
+  FRBX_IN_C32 = 1,   /* (re, im) float16 pairs */
+  FRBX_IN_E4M3 = 2   /* (re, im) OCP FP8 e4m3 byte pairs, value = decoded x scale[b][n][j] */
+} frbx_input_kind;
+
+frbx_status frbx_stream_begin(frbx_ctx *ctx, int64_t chunk_frames);
+
+/* One chunk [B][N][J][chunk_frames] of `kind`; scale: float32 [B][N][J] for
+ * FRBX_IN_E4M3 (else ignored), on the same side (host / device) as the
+ * chunk.  Host chunks are copied; device chunks are read before the call
+ * returns. */
+frbx_status frbx_stream_push(frbx_ctx *ctx, const void *chunk, int32_t kind, const float *scale,
+                             int is_device);
+
+/* Stream position: APs pushed so far, and per window (arrays of the number
+ * of windows, may be NULL) the global index of the first segment and the
+ * number of segments of the last push. */
+frbx_status frbx_stream_position(const frbx_ctx *ctx, int64_t *frames_in, int64_t *first_segment,
+                                 int64_t *n_segments);
+
 /* Multiple-baselines power summation scheme (Sec. 2.4.2), after frbx_run:
  * the powers of corresponding segments of the listed baselines are summed,
  * normalised per (DM trial, window) with Eq. 6, thresholded, and filtered

@@ -105,6 +105,20 @@ struct frbx_ctx {
   std::vector<Span> spans;
   frbx_timing last_timing{};
 
+  int64_t cube_len = 0;       // segments per (b, d) of the last pass
+  std::vector<int> last_off, last_nq;  // window offsets / counts of the last pass
+
+  // streaming state
+  bool streaming = false;
+  int64_t chunk = 0, carry = 0, buf_frames = 0, valid = 0, buf_start = 0, frames_in = 0;
+  float2 *sbuf[2] = {nullptr, nullptr};
+  int cur = 0;
+  void *stage = nullptr;
+  size_t stage_cap = 0;
+  float *d_scale = nullptr;
+  std::vector<int64_t> next_q, push_first, push_nq;
+  std::vector<frbx_candidate> stream_cross;
+
   // results
   bool have = false;
   std::vector<double> mean, sd;
@@ -159,6 +173,10 @@ struct frbx_ctx {
     hipSetDevice(device);
     for (hipEvent_t e : ev_pool) hipEventDestroy(e);
     dfree(d_vis_own);
+    dfree(sbuf[0]);
+    dfree(sbuf[1]);
+    dfree(stage);
+    dfree(d_scale);
     dfree(d_mfma_hi);
     dfree(d_mfma_lo);
     dfree(d_absmax);
@@ -762,23 +780,35 @@ frbx_status frbx_set_precision(frbx_ctx *c, int32_t precision) {
   return FRBX_OK;
 }
 
-frbx_status frbx_run(frbx_ctx *c) {
-  if (!c) return FRBX_E_INVAL;
-  if (!c->loaded) return c->fail(FRBX_E_STATE, "frbx_run before frbx_load");
-  if (hipSetDevice(c->device) != hipSuccess) return c->fail(FRBX_E_DEVICE, "hipSetDevice failed");
-  c->have = false;
-  c->spans.clear();
-  c->ev_used = 0;
-  frbx_status s = prepare(c);
-  if (s != FRBX_OK) return s;
+}  // extern "C"
+
+namespace {
+
+// One pass of the device search over APs [0, K) of an input buffer
+// (complex64 / complex32, layout [B][N J][K]) with, per window, segments
+// k0 = k0_w + q hop_w for q < nq_w: dedispersion and fringe search per
+// (baseline, DM tile), Eq. 6 statistics and threshold over each window's
+// segments of this pass.  Leaves the cube in d_power / d_pidx ([B][D][S]),
+// the statistics in c->mean / sd / cnt and the crossings (local q) in `hc`.
+struct PassSpec {
+  const void *vis;
+  int vis_f16;
+  int64_t K;        // APs available per channel
+  int64_t stride;   // elements between channel rows
+  std::vector<int> k0, nq, off;
+  int64_t S;
+};
+
+frbx_status device_pass(frbx_ctx *c, const PassSpec &ps, std::vector<DevCrossing> &hc) {
+  frbx_status s;
   const int B = c->B, D = c->n_dm, NJ = c->N * c->J, nw = int(c->windows.size());
-  const int64_t S = c->seg_total;
-  // workspaces
-  const size_t per_dm = size_t(std::max<int64_t>(c->k_eff, 0)) * NJ;
+  const int64_t S = ps.S;
+  const int64_t k_eff = ps.K - c->dk_max;
+  const size_t per_dm = size_t(std::max<int64_t>(k_eff, 0)) * NJ;
   c->dt = per_dm ? int(std::max<size_t>(1, std::min<size_t>(D, c->w_budget / (per_dm * sizeof(float2))))) : 1;
   while (c->dt > 1 && int64_t(c->dt) * S > (int64_t(1) << 31) - 1) c->dt /= 2;
   if ((s = ensure(c, c->d_w, c->w_cap, per_dm * c->dt)) != FRBX_OK) return s;
-  const size_t cube = size_t(B) * D * S;
+  const size_t cube = size_t(B) * D * std::max<int64_t>(S, 1);
   if ((s = ensure(c, c->d_power, c->cube_cap, cube)) != FRBX_OK) return s;
   if ((s = ensure(c, c->d_pidx, c->pidx_cap, cube)) != FRBX_OK) return s;
   const size_t rows = size_t(B) * D * nw;
@@ -801,32 +831,33 @@ frbx_status frbx_run(frbx_ctx *c) {
   const size_t lds = use_mfma ? frbx::fringe_mfma_lds_bytes(J, c->N, c->sbd_pad, n_pass)
                               : frbx::fringe_lds_bytes(J, M, c->N, c->sbd_pad);
   const float scale = mfma_scale(c);
-  if (S > 0 && c->k_eff > 0) {
+  const size_t in_bytes = ps.vis_f16 ? 4 : 8;
+  if (S > 0 && k_eff > 0) {
     for (int b = 0; b < B; ++b) {
       for (int d0 = 0; d0 < D; d0 += c->dt) {
         const int ndt = std::min(c->dt, D - d0);
         frbx::DedisperseArgs da{};
-        da.vis = static_cast<const char *>(c->d_vis) + size_t(b) * NJ * size_t(c->K) * (c->vis_f16 ? 4 : 8);
-        da.in_f16 = c->vis_f16;
-        da.n_frames = c->K;
+        da.vis = static_cast<const char *>(ps.vis) + size_t(b) * NJ * size_t(ps.stride) * in_bytes;
+        da.in_f16 = ps.vis_f16;
+        da.n_frames = ps.K;
+        da.row_stride = ps.stride;
         da.dk = c->d_dk;
         da.d0 = d0;
         da.n_dt = ndt;
         da.cal = c->d_cal + size_t(b) * NJ;
         da.out = c->d_w;
-        da.k_eff = c->k_eff;
+        da.k_eff = k_eff;
         da.nj = NJ;
         da.group = c->dd_group;
-        int sp = c->span_begin(1, int64_t(ndt) * c->k_eff);
+        int sp = c->span_begin(1, int64_t(ndt) * k_eff);
         if (sp >= 0) {
           // writes: ndt x k_eff spectra; reads: each channel's span of
           // k_eff + (offset spread of the group) APs once per group
-          int64_t bytes = int64_t(ndt) * c->k_eff * NJ * 8;
-          const int in_b = c->vis_f16 ? 4 : 8;
+          int64_t bytes = int64_t(ndt) * k_eff * NJ * 8;
           for (int g0 = 0; g0 < ndt; g0 += c->dd_group) {
             const int g1 = std::min(ndt, g0 + c->dd_group) - 1;
             const int32_t *a0 = c->dk.data() + size_t(d0 + g0) * NJ, *a1 = c->dk.data() + size_t(d0 + g1) * NJ;
-            for (int i = 0; i < NJ; ++i) bytes += (c->k_eff + (a1[i] - a0[i])) * in_b;
+            for (int i = 0; i < NJ; ++i) bytes += (k_eff + (a1[i] - a0[i])) * int64_t(in_bytes);
           }
           c->spans[sp].bytes = bytes;
         }
@@ -834,7 +865,7 @@ frbx_status frbx_run(frbx_ctx *c) {
         c->span_end(sp);
         frbx::FringeArgs fa{};
         fa.w = c->d_w;
-        fa.w_dm_stride = c->k_eff * NJ;
+        fa.w_dm_stride = k_eff * NJ;
         fa.n_if = c->N;
         fa.n_rate = c->n_rate;
         fa.sbd_pad = c->sbd_pad;
@@ -842,7 +873,8 @@ frbx_status frbx_run(frbx_ctx *c) {
         for (int w = 0; w < nw; ++w) {
           fa.win_len[w] = c->windows[w];
           fa.win_hop[w] = c->hop[w];
-          fa.win_off[w] = c->segoff[w];
+          fa.win_off[w] = ps.off[w];
+          fa.win_k0[w] = ps.k0[w];
           fa.rate_off[w] = c->rate_off[w];
         }
         fa.seg_total = int(S);
@@ -874,8 +906,8 @@ frbx_status frbx_run(frbx_ctx *c) {
   st.seg_total = int(S);
   st.n_win = nw;
   for (int w = 0; w < nw; ++w) {
-    st.win_off[w] = c->segoff[w];
-    st.win_q[w] = c->nseg[w];
+    st.win_off[w] = ps.off[w];
+    st.win_q[w] = ps.nq[w];
   }
   st.threshold = c->threshold;
   st.mean = c->d_mean;
@@ -905,7 +937,7 @@ frbx_status frbx_run(frbx_ctx *c) {
     st.cap = c->cross_cap;
   }
   if (c->timing) c->collect_timing();
-  std::vector<DevCrossing> hc(ncr);
+  hc.assign(ncr, DevCrossing{});
   c->mean.assign(rows, 0.0);
   c->sd.assign(rows, 0.0);
   c->cnt.assign(rows, 0);
@@ -921,35 +953,207 @@ frbx_status frbx_run(frbx_ctx *c) {
   std::sort(hc.begin(), hc.end(), [](const DevCrossing &x, const DevCrossing &y) {
     return x.row != y.row ? x.row < y.row : x.q < y.q;
   });
-  const int PJ = c->sbd_pad * J;
+  c->cube_len = S;
+  c->last_off = ps.off;
+  c->last_nq = ps.nq;
+  return FRBX_OK;
+}
+
+// crossing record of segment q_global of window w
+frbx_candidate make_crossing(const frbx_ctx *c, const DevCrossing &x, int64_t q_global) {
+  const int nw = int(c->windows.size()), D = c->n_dm, M = c->n_mbd, PJ = c->sbd_pad * c->J;
+  frbx_candidate k{};
+  const int w = x.row % nw, bd = x.row / nw;
+  k.baseline = bd / D;
+  k.dm_index = bd % D;
+  k.window_index = w;
+  k.window_len = c->windows[w];
+  k.segment = q_global;
+  k.k0 = q_global * c->hop[w];
+  k.dm = c->dm_lo + k.dm_index * c->dm_step;
+  k.power = x.power;
+  k.power_norm = x.pnorm;
+  const int m = x.idx % M, sb = (x.idx / M) % PJ, r = x.idx / (M * PJ);
+  k.rate_idx = r;
+  k.sbd_idx = sb;
+  k.mbd_idx = m;
+  k.rate = (r - c->n_rate / 2) * c->rate_step;
+  k.sbd_us = (sb - PJ / 2.0) / (PJ * c->df);
+  k.mbd_us = (m - M / 2.0) * c->mbd_step;
+  k.n_windows = 0;
+  k.group_id = -1;
+  return k;
+}
+
+}  // namespace
+
+extern "C" {
+
+frbx_status frbx_run(frbx_ctx *c) {
+  if (!c) return FRBX_E_INVAL;
+  if (!c->loaded) return c->fail(FRBX_E_STATE, "frbx_run before frbx_load");
+  if (hipSetDevice(c->device) != hipSuccess) return c->fail(FRBX_E_DEVICE, "hipSetDevice failed");
+  c->have = false;
+  c->spans.clear();
+  c->ev_used = 0;
+  frbx_status s = prepare(c);
+  if (s != FRBX_OK) return s;
+  c->streaming = false;
+  const int nw = int(c->windows.size());
+  PassSpec ps;
+  ps.vis = c->d_vis;
+  ps.vis_f16 = c->vis_f16;
+  ps.K = c->K;
+  ps.stride = c->K;
+  ps.k0.assign(nw, 0);
+  ps.nq = c->nseg;
+  ps.off = c->segoff;
+  ps.S = c->seg_total;
+  std::vector<DevCrossing> hc;
+  if ((s = device_pass(c, ps, hc)) != FRBX_OK) return s;
   c->cross.clear();
   c->cross.reserve(hc.size());
-  for (const DevCrossing &x : hc) {
-    frbx_candidate k{};
-    const int w = x.row % nw, bd = x.row / nw;
-    k.baseline = bd / D;
-    k.dm_index = bd % D;
-    k.window_index = w;
-    k.window_len = c->windows[w];
-    k.segment = x.q;
-    k.k0 = int64_t(x.q) * c->hop[w];
-    k.dm = c->dm_lo + k.dm_index * c->dm_step;
-    k.power = x.power;
-    k.power_norm = x.pnorm;
-    const int m = x.idx % M, sb = (x.idx / M) % PJ, r = x.idx / (M * PJ);
-    k.rate_idx = r;
-    k.sbd_idx = sb;
-    k.mbd_idx = m;
-    k.rate = (r - c->n_rate / 2) * c->rate_step;
-    k.sbd_us = (sb - PJ / 2.0) / (PJ * c->df);
-    k.mbd_us = (m - M / 2.0) * c->mbd_step;
-    k.n_windows = 0;
-    k.group_id = -1;
-    c->cross.push_back(k);
-  }
+  for (const DevCrossing &x : hc) c->cross.push_back(make_crossing(c, x, x.q));
   detect_impl(c->cross.data(), int64_t(c->cross.size()), c->t_amb, c->n_win_min, c->n_bl_min, true,
               c->dets, c->groups);
   c->have = true;
+  return FRBX_OK;
+}
+
+frbx_status frbx_stream_begin(frbx_ctx *c, int64_t chunk_frames) {
+  if (!c) return FRBX_E_INVAL;
+  if (chunk_frames < 1) return c->fail(FRBX_E_INVAL, "chunk_frames must be >= 1");
+  if (hipSetDevice(c->device) != hipSuccess) return c->fail(FRBX_E_DEVICE, "hipSetDevice failed");
+  frbx_status s = prepare(c);
+  if (s != FRBX_OK) return s;
+  int lmax = 1;
+  for (int l : c->windows) lmax = std::max(lmax, l);
+  c->chunk = chunk_frames;
+  c->carry = c->dk_max + lmax - 1;
+  c->buf_frames = c->carry + chunk_frames;
+  const size_t n = size_t(c->B) * c->N * c->J * size_t(c->buf_frames);
+  for (int i = 0; i < 2; ++i) {
+    dfree(c->sbuf[i]);
+    if (hipMalloc(reinterpret_cast<void **>(&c->sbuf[i]), n * sizeof(float2)) != hipSuccess)
+      return c->fail(FRBX_E_NOMEM, "device allocation for the stream buffers failed");
+    if ((s = c->hip(hipMemset(c->sbuf[i], 0, n * sizeof(float2)), "memset")) != FRBX_OK) return s;
+  }
+  c->cur = 0;
+  c->valid = c->buf_start = c->frames_in = 0;
+  const int nw = int(c->windows.size());
+  c->next_q.assign(nw, 0);
+  c->push_first.assign(nw, 0);
+  c->push_nq.assign(nw, 0);
+  c->stream_cross.clear();
+  c->streaming = true;
+  c->have = false;
+  return FRBX_OK;
+}
+
+frbx_status frbx_stream_push(frbx_ctx *c, const void *chunk, int32_t kind, const float *scale, int is_device) {
+  if (!c) return FRBX_E_INVAL;
+  if (!c->streaming) return c->fail(FRBX_E_STATE, "frbx_stream_push before frbx_stream_begin");
+  if (c->dirty) return c->fail(FRBX_E_STATE, "grids changed since frbx_stream_begin");
+  if (!chunk || kind < FRBX_IN_C64 || kind > FRBX_IN_E4M3 || (kind == FRBX_IN_E4M3 && !scale))
+    return c->fail(FRBX_E_INVAL, "bad chunk, kind or scale");
+  if (hipSetDevice(c->device) != hipSuccess) return c->fail(FRBX_E_DEVICE, "hipSetDevice failed");
+  c->have = false;
+  c->spans.clear();
+  c->ev_used = 0;
+  frbx_status s;
+  const int NJ = c->N * c->J, rows = c->B * NJ, nw = int(c->windows.size());
+  const size_t elem = kind == FRBX_IN_C64 ? 8 : kind == FRBX_IN_C32 ? 4 : 2;
+  const size_t bytes = size_t(rows) * size_t(c->chunk) * elem;
+  const void *src = chunk;
+  const float *sc = scale;
+  if (!is_device) {
+    if ((s = ensure(c, reinterpret_cast<char *&>(c->stage), c->stage_cap, bytes)) != FRBX_OK) return s;
+    if ((s = c->hip(hipMemcpyAsync(c->stage, chunk, bytes, hipMemcpyHostToDevice, c->stream), "chunk upload")) != FRBX_OK)
+      return s;
+    src = c->stage;
+    if (kind == FRBX_IN_E4M3) {
+      if (!c->d_scale && hipMalloc(reinterpret_cast<void **>(&c->d_scale), size_t(rows) * sizeof(float)) != hipSuccess)
+        return c->fail(FRBX_E_NOMEM, "device allocation failed");
+      if ((s = c->hip(hipMemcpyAsync(c->d_scale, scale, size_t(rows) * sizeof(float), hipMemcpyHostToDevice, c->stream),
+                      "scale upload")) != FRBX_OK)
+        return s;
+      sc = c->d_scale;
+    }
+  }
+  // carry the last dk_max + l_max - 1 APs into the other buffer, append the chunk
+  const int other = 1 - c->cur;
+  const int64_t keep = std::min(c->carry, c->valid);
+  if ((s = c->hip(frbx::launch_carry(c->sbuf[c->cur], c->sbuf[other], rows, c->buf_frames, c->valid - keep, keep,
+                                     c->stream), "carry")) != FRBX_OK)
+    return s;
+  if ((s = c->hip(frbx::launch_ingest(src, kind, sc, c->chunk, rows, c->sbuf[other], c->buf_frames, keep, c->stream),
+                  "ingest")) != FRBX_OK)
+    return s;
+  c->buf_start = c->frames_in == 0 ? 0 : c->buf_start + c->valid - keep;
+  c->valid = keep + c->chunk;
+  c->cur = other;
+  c->frames_in += c->chunk;
+  // float16 operand scale of the matrix-core forms from this buffer
+  if (c->precision != FRBX_PREC_F32) {
+    if (!c->d_absmax && hipMalloc(reinterpret_cast<void **>(&c->d_absmax), sizeof(unsigned int)) != hipSuccess)
+      return c->fail(FRBX_E_NOMEM, "device allocation failed");
+    unsigned int am = 0;
+    s = c->hip(hipMemsetAsync(c->d_absmax, 0, sizeof(unsigned int), c->stream), "memset");
+    if (s == FRBX_OK)
+      s = c->hip(frbx::launch_absmax(c->sbuf[c->cur], int64_t(rows) * c->buf_frames, 0, c->d_absmax, c->stream), "absmax");
+    if (s == FRBX_OK) s = c->hip(hipMemcpyAsync(&am, c->d_absmax, sizeof(am), hipMemcpyDeviceToHost, c->stream), "absmax");
+    if (s == FRBX_OK) s = c->hip(hipStreamSynchronize(c->stream), "absmax");
+    if (s != FRBX_OK) return s;
+    std::memcpy(&c->vis_absmax, &am, sizeof(float));
+  }
+  // the segments this push completes
+  PassSpec ps;
+  ps.vis = c->sbuf[c->cur];
+  ps.vis_f16 = 0;
+  ps.K = c->valid;
+  ps.stride = c->buf_frames;
+  ps.k0.assign(nw, 0);
+  ps.nq.assign(nw, 0);
+  ps.off.assign(nw, 0);
+  int64_t tot = 0;
+  for (int w = 0; w < nw; ++w) {
+    const int l = c->windows[w], h = c->hop[w];
+    const int64_t last = c->buf_start + c->valid - c->dk_max - l;  // latest complete start AP
+    const int64_t qhi = last >= 0 ? last / h : -1;
+    const int64_t nq = std::max<int64_t>(0, qhi - c->next_q[w] + 1);
+    const int64_t k0 = c->next_q[w] * h - c->buf_start;
+    if (nq > 0 && k0 < 0) return c->fail(FRBX_E_STATE, "stream carry too short");
+    ps.k0[w] = int(std::max<int64_t>(k0, 0));
+    ps.nq[w] = int(nq);
+    ps.off[w] = int(tot);
+    tot += nq;
+    c->push_first[w] = c->next_q[w];
+    c->push_nq[w] = nq;
+  }
+  ps.S = tot;
+  std::vector<DevCrossing> hc;
+  if ((s = device_pass(c, ps, hc)) != FRBX_OK) return s;
+  c->cross.clear();
+  for (const DevCrossing &x : hc) {
+    const int w = x.row % nw;
+    c->cross.push_back(make_crossing(c, x, c->push_first[w] + x.q));
+  }
+  for (int w = 0; w < nw; ++w) c->next_q[w] += c->push_nq[w];
+  c->stream_cross.insert(c->stream_cross.end(), c->cross.begin(), c->cross.end());
+  detect_impl(c->stream_cross.data(), int64_t(c->stream_cross.size()), c->t_amb, c->n_win_min, c->n_bl_min, true,
+              c->dets, c->groups);
+  c->have = true;
+  return FRBX_OK;
+}
+
+frbx_status frbx_stream_position(const frbx_ctx *c, int64_t *frames_in, int64_t *first, int64_t *nseg) {
+  if (!c) return FRBX_E_INVAL;
+  if (!c->streaming) return FRBX_E_STATE;
+  if (frames_in) *frames_in = c->frames_in;
+  for (size_t w = 0; w < c->windows.size(); ++w) {
+    if (first) first[w] = c->push_first[w];
+    if (nseg) nseg[w] = c->push_nq[w];
+  }
   return FRBX_OK;
 }
 
@@ -979,7 +1183,7 @@ frbx_status frbx_get_ap_offsets(const frbx_ctx *cc, int32_t *out, int64_t cap, i
 frbx_status frbx_get_power_cube(const frbx_ctx *c, float *power, int32_t *idx, int64_t cap, int64_t *n) {
   if (!c) return FRBX_E_INVAL;
   if (!c->have) return FRBX_E_STATE;
-  const int64_t len = int64_t(c->B) * c->n_dm * c->seg_total;
+  const int64_t len = int64_t(c->B) * c->n_dm * c->cube_len;
   if (n) *n = len;
   if (cap < len) return FRBX_E_RANGE;
   hipSetDevice(c->device);
@@ -1046,6 +1250,7 @@ frbx_status frbx_dump_segment(frbx_ctx *c, int32_t b, int32_t d, int32_t w, int6
   da.vis = static_cast<const char *>(c->d_vis) + size_t(b) * NJ * size_t(c->K) * (c->vis_f16 ? 4 : 8);
   da.in_f16 = c->vis_f16;
   da.n_frames = c->K;
+  da.row_stride = c->K;
   da.dk = c->d_dk;
   da.d0 = d;
   da.n_dt = 1;
@@ -1106,8 +1311,9 @@ frbx_status frbx_power_sum(frbx_ctx *c, const int32_t *bl, int32_t n_bl, frbx_ca
   }
   if (hipSetDevice(c->device) != hipSuccess) return c->fail(FRBX_E_DEVICE, "hipSetDevice failed");
   const int D = c->n_dm, nw = int(c->windows.size());
-  const int64_t S = c->seg_total, len = int64_t(D) * S;
+  const int64_t S = c->cube_len, len = int64_t(D) * S;
   const int rows = D * nw;
+  const int64_t bl_stride = int64_t(D) * S;
   std::vector<frbx_candidate> cross;
   if (S > 0) {
     float *d_sum = nullptr;
@@ -1124,15 +1330,15 @@ frbx_status frbx_power_sum(frbx_ctx *c, const int32_t *bl, int32_t n_bl, frbx_ca
       return c->fail(FRBX_E_NOMEM, "device allocation failed");
     }
     frbx_status s = c->hip(hipMemcpy(d_bl, bl, size_t(n_bl) * sizeof(int32_t), hipMemcpyHostToDevice), "copy");
-    if (s == FRBX_OK) s = c->hip(frbx::launch_cube_sum(c->d_power, len, d_bl, n_bl, d_sum, len, c->stream), "sum launch");
+    if (s == FRBX_OK) s = c->hip(frbx::launch_cube_sum(c->d_power, bl_stride, d_bl, n_bl, d_sum, len, c->stream), "sum launch");
     frbx::StatsArgs st{};
     st.power = d_sum;
     st.pidx = c->d_pidx;
     st.seg_total = int(S);
     st.n_win = nw;
     for (int w = 0; w < nw; ++w) {
-      st.win_off[w] = c->segoff[w];
-      st.win_q[w] = c->nseg[w];
+      st.win_off[w] = c->last_off[w];
+      st.win_q[w] = c->last_nq[w];
     }
     st.threshold = c->threshold;
     st.mean = d_m;
@@ -1174,8 +1380,9 @@ frbx_status frbx_power_sum(frbx_ctx *c, const int32_t *bl, int32_t n_bl, frbx_ca
       k.dm_index = x.row / nw;
       k.window_index = w;
       k.window_len = c->windows[w];
-      k.segment = x.q;
-      k.k0 = int64_t(x.q) * c->hop[w];
+      const int64_t qg = (c->streaming ? c->push_first[w] : 0) + x.q;
+      k.segment = qg;
+      k.k0 = qg * c->hop[w];
       k.dm = c->dm_lo + k.dm_index * c->dm_step;
       k.power = x.power;
       k.power_norm = x.pnorm;

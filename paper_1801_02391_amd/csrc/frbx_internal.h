@@ -25,7 +25,8 @@ struct DedisperseArgs {
   const void *vis;     // [NJ][K] of this baseline: complex64, or complex32
                        // (two float16) when in_f16
   int32_t in_f16;
-  int64_t n_frames;    // K
+  int64_t n_frames;    // K: APs available per channel
+  int64_t row_stride;  // elements between channel rows (>= n_frames)
   const int32_t *dk;   // [D][NJ]
   int32_t d0;          // first DM trial of the tile
   int32_t n_dt;        // DM trials in the tile
@@ -58,6 +59,7 @@ struct FringeArgs {
   int32_t win_len[kMaxWindows];
   int32_t win_hop[kMaxWindows];
   int32_t win_off[kMaxWindows];   // first cube segment of the window
+  int32_t win_k0[kMaxWindows];    // AP of the window's first segment (k0 = win_k0 + q hop)
   int32_t rate_off[kMaxWindows];  // offset (float2) of the window's [R][N][l] phasors
   int32_t seg_total;               // segments per (b, d)
   int32_t n_dt;                    // DM trials in this launch
@@ -121,6 +123,15 @@ hipError_t launch_cube_sum(const float *power, int64_t bl_stride, const int32_t 
 // c over n_chan_total channels of one baseline
 hipError_t launch_segment_sum(const void *vis, int in_f16, int64_t n_frames, int n_ch, int64_t k0,
                               int len, float2 *out, hipStream_t s);
+
+// streaming input: dst[c][k0 + k] = complex64 of src[c][k] for k < n_frames
+// (src complex64, complex32, or FP8 e4m3 pairs times scale[c]); channel c
+// over n_ch, dst row stride dst_frames
+hipError_t launch_ingest(const void *src, int src_kind, const float *scale, int64_t n_frames, int n_ch,
+                         float2 *dst, int64_t dst_frames, int64_t k0, hipStream_t s);
+// dst[c][k] = src[c][from + k] for k < n (the carry into the other buffer)
+hipError_t launch_carry(const float2 *src, float2 *dst, int n_ch, int64_t frames, int64_t from, int64_t n,
+                        hipStream_t s);
 
 // max(|re|, |im|) over n complex values (float32 or float16 pairs) into
 // *out (float bits, caller zeroes it first)

@@ -280,7 +280,7 @@ __global__ __launch_bounds__(kBlock) void dedisperse_kernel(DedisperseArgs a) {
     if (c >= a.nj) continue;
     const int64_t base = kt + dk0[c];
     const int span = kDedispAp + (dk1[c] - dk0[c]);
-    const int64_t row = int64_t(c) * a.n_frames;
+    const int64_t row = int64_t(c) * a.row_stride;
     for (int x = lane; x < span; x += 64) {
       const int64_t f = base + x;
       tile[i][x] = f < a.n_frames ? load_vis(a.vis, row + f, F16) : make_float2(0.f, 0.f);
@@ -323,7 +323,7 @@ __global__ __launch_bounds__(kBlock) void fringe_kernel(FringeArgs a) {
   while (wi + 1 < a.n_win && a.win_off[wi + 1] <= seg) ++wi;
   const int l = a.win_len[wi];
   const int q = seg - a.win_off[wi];
-  const int64_t k0 = int64_t(q) * a.win_hop[wi];
+  const int64_t k0 = a.win_k0[wi] + int64_t(q) * a.win_hop[wi];
   const float2 *wd = a.w + int64_t(dl) * a.w_dm_stride + k0 * NJ;
   const float2 *rph = a.rate_ph + a.rate_off[wi];
 
@@ -609,7 +609,7 @@ __global__ __launch_bounds__(kBlock) void fringe_mfma_kernel(FringeArgs a) {
   while (wi + 1 < a.n_win && a.win_off[wi + 1] <= seg) ++wi;
   const int l = a.win_len[wi];
   const int q = seg - a.win_off[wi];
-  const int64_t k0 = int64_t(q) * a.win_hop[wi];
+  const int64_t k0 = a.win_k0[wi] + int64_t(q) * a.win_hop[wi];
   const float2 *wd = a.w + int64_t(dl) * a.w_dm_stride + k0 * NJ;
   const float2 *rph = a.rate_ph + a.rate_off[wi];
 
@@ -795,6 +795,45 @@ __global__ __launch_bounds__(kBlock) void segment_sum_kernel(const void *vis, in
     acc.y += __shfl_xor(acc.y, off, 64);
   }
   if (lane == 0) out[c] = acc;
+}
+
+// OCP FP8 e4m3 (e4m3fn): sign, 4-bit exponent (bias 7), 3-bit mantissa, no
+// infinities, 0x7f / 0xff are NaN; decoded exactly into float32.
+__device__ __forceinline__ float fp8_e4m3(unsigned b) {
+  const unsigned e = (b >> 3) & 15u, m = b & 7u;
+  float v;
+  if (e == 15u && m == 7u) v = __builtin_nanf("");
+  else if (e == 0u) v = float(m) * 0.001953125f;           // m 2^-9
+  else v = __uint_as_float(((e + 120u) << 23) | (m << 20));  // (1 + m/8) 2^(e-7)
+  return (b & 128u) ? -v : v;
+}
+
+__global__ __launch_bounds__(kBlock) void ingest_kernel(const void *src, int kind, const float *scale,
+                                                        int64_t n_frames, int n_ch, float2 *dst,
+                                                        int64_t dst_frames, int64_t k0) {
+  const int c = blockIdx.y;
+  const float sc = kind == 2 ? scale[c] : 1.0f;
+  float2 *d = dst + int64_t(c) * dst_frames + k0;
+  for (int64_t k = int64_t(blockIdx.x) * kBlock + threadIdx.x; k < n_frames;
+       k += int64_t(gridDim.x) * kBlock) {
+    const int64_t i = int64_t(c) * n_frames + k;
+    float2 v;
+    if (kind == 2) {
+      const unsigned short w = static_cast<const unsigned short *>(src)[i];
+      v = make_float2(fp8_e4m3(w & 255u) * sc, fp8_e4m3(w >> 8) * sc);
+    } else {
+      v = load_vis(src, i, kind == 1);
+    }
+    d[k] = v;
+  }
+}
+
+__global__ __launch_bounds__(kBlock) void carry_kernel(const float2 *src, float2 *dst, int64_t frames,
+                                                       int64_t from, int64_t n) {
+  const float2 *s = src + int64_t(blockIdx.y) * frames + from;
+  float2 *d = dst + int64_t(blockIdx.y) * frames;
+  for (int64_t k = int64_t(blockIdx.x) * kBlock + threadIdx.x; k < n; k += int64_t(gridDim.x) * kBlock)
+    d[k] = s[k];
 }
 
 __global__ __launch_bounds__(kBlock) void absmax_kernel(const void *vis, int64_t n, int in_f16,
@@ -1004,6 +1043,27 @@ hipError_t launch_segment_sum(const void *vis, int in_f16, int64_t n_frames, int
   const int blocks = (n_ch + kBlock / 64 - 1) / (kBlock / 64);
   hipLaunchKernelGGL(segment_sum_kernel, dim3(blocks), dim3(kBlock), 0, s, vis, in_f16, n_frames, n_ch,
                      k0, len, out);
+  return hipGetLastError();
+}
+
+hipError_t launch_ingest(const void *src, int src_kind, const float *scale, int64_t n_frames, int n_ch,
+                         float2 *dst, int64_t dst_frames, int64_t k0, hipStream_t s) {
+  (void)hipGetLastError();
+  if (n_frames <= 0 || n_ch <= 0) return hipSuccess;
+  const int64_t bx = std::min<int64_t>(64, (n_frames + kBlock - 1) / kBlock);
+  hipLaunchKernelGGL(ingest_kernel, dim3(unsigned(bx), unsigned(n_ch)), dim3(kBlock), 0, s, src, src_kind,
+                     scale, n_frames, n_ch, dst, dst_frames, k0);
+  return hipGetLastError();
+}
+
+hipError_t launch_carry(const float2 *src, float2 *dst, int n_ch, int64_t frames, int64_t from, int64_t n,
+                        hipStream_t s) {
+  (void)hipGetLastError();
+  if (n <= 0 || n_ch <= 0) return hipSuccess;
+  if (src == dst) return hipErrorInvalidValue;
+  const int64_t bx = std::min<int64_t>(64, (n + kBlock - 1) / kBlock);
+  hipLaunchKernelGGL(carry_kernel, dim3(unsigned(bx), unsigned(n_ch)), dim3(kBlock), 0, s, src, dst, frames,
+                     from, n);
   return hipGetLastError();
 }
 

@@ -82,6 +82,9 @@ _SIGS = {
     "frbx_get_groups": ([_P, _P, C.c_int64, _P], C.c_int),
     "frbx_dump_segment": ([_P, C.c_int32, C.c_int32, C.c_int32, C.c_int64, _P], C.c_int),
     "frbx_set_timing": ([_P, C.c_int], C.c_int),
+    "frbx_stream_begin": ([_P, C.c_int64], C.c_int),
+    "frbx_stream_push": ([_P, _P, C.c_int32, _P, C.c_int], C.c_int),
+    "frbx_stream_position": ([_P, _P, _P, _P], C.c_int),
     "frbx_power_sum": ([_P, _P, C.c_int32, _P, C.c_int64, _P], C.c_int),
     "frbx_calibrate": ([_P, C.c_int32, C.c_int64, C.c_int32, _P, _P], C.c_int),
     "frbx_get_timing": ([_P, _P], C.c_int),
@@ -328,6 +331,40 @@ class Search:
         arr = (Group * max(1, n.value))()
         self._chk(L.frbx_get_groups(self._h, arr, n.value, C.byref(n)), "get_groups")
         return [{f: getattr(arr[i], f) for f, _ in Group._fields_} for i in range(n.value)]
+
+    # ------------------------------------------------------------ streaming
+    _KINDS = {"c64": 0, "c32": 1, "e4m3": 2}
+
+    def stream_begin(self, chunk_frames):
+        self._chk(lib().frbx_stream_begin(self._h, int(chunk_frames)), "stream_begin")
+
+    def stream_push(self, chunk, kind="c64", scale=None):
+        """chunk: [B][N][J][chunk] complex64, float16 [..][2] (c32) or uint8
+        [..][2] (e4m3, with float32 scale [B][N][J]); torch (device) or numpy."""
+        torch = self._torch
+        k = self._KINDS[kind]
+        if isinstance(chunk, torch.Tensor):
+            if not chunk.is_contiguous() or chunk.device.type != "cuda":
+                raise FrbxError(E_INVAL, "chunk must be a contiguous GPU tensor")
+            sp = None
+            if k == 2:
+                if not isinstance(scale, torch.Tensor) or scale.dtype != torch.float32:
+                    raise FrbxError(E_INVAL, "e4m3 chunks need a float32 scale tensor")
+                sp = _P(scale.contiguous().data_ptr())
+            self._chk(lib().frbx_stream_push(self._h, _P(chunk.data_ptr()), k, sp, 1), "stream_push")
+        else:
+            a = np.ascontiguousarray(chunk)
+            sc = None if scale is None else np.ascontiguousarray(scale, dtype=np.float32)
+            self._chk(lib().frbx_stream_push(self._h, _ptr(a), k, _ptr(sc), 0), "stream_push")
+
+    def stream_position(self):
+        nw = len(self._windows)
+        fi = C.c_int64(0)
+        first = np.zeros(nw, dtype=np.int64)
+        nseg = np.zeros(nw, dtype=np.int64)
+        self._chk(lib().frbx_stream_position(self._h, C.byref(fi), _ptr(first), _ptr(nseg)),
+                  "stream_position")
+        return dict(frames_in=fi.value, first=first.tolist(), n_seg=nseg.tolist())
 
     def power_sum(self, baselines):
         """Sec. 2.4.2 detections from the summed power of `baselines`."""

@@ -119,6 +119,51 @@ def from_complex32(H):
     return (H[..., 0].astype(np.float32) + 1j * H[..., 1].astype(np.float32)).astype(np.complex64)
 
 
+def _e4m3_table():
+    """Values of the 256 OCP FP8 e4m3 (e4m3fn) codes (NaN for 0x7f, 0xff)."""
+    v = np.zeros(256)
+    for b in range(256):
+        e, m = (b >> 3) & 15, b & 7
+        if e == 15 and m == 7:
+            x = np.nan
+        elif e == 0:
+            x = m * 2.0 ** -9
+        else:
+            x = (1 + m / 8) * 2.0 ** (e - 7)
+        v[b] = -x if b & 128 else x
+    return v
+
+
+E4M3 = _e4m3_table()
+
+
+def to_e4m3(V):
+    """complex64 [B][N][J][K] -> (uint8 codes [B][N][J][K][2], float32 scale
+    [B][N][J]): the FP8 storage form, one scale per channel = max|re, im| / 448,
+    each component rounded to the nearest e4m3 value (ties to even code)."""
+    amax = np.maximum(np.abs(V.real), np.abs(V.imag)).max(axis=-1)
+    scale = np.where(amax > 0, amax / 448.0, 1.0).astype(np.float32)
+    pos = E4M3[:127]                        # codes 0..126, increasing
+    out = np.empty(V.shape + (2,), dtype=np.uint8)
+    for comp, part in ((0, V.real), (1, V.imag)):
+        x = (part / scale[..., None]).astype(np.float64)
+        a = np.minimum(np.abs(x), 448.0)
+        hi = np.clip(np.searchsorted(pos, a, side="left"), 1, 126)
+        lo = hi - 1
+        dlo, dhi = a - pos[lo], pos[hi] - a
+        pick = np.where((dhi < dlo) | ((dhi == dlo) & (hi % 2 == 0)), hi, lo)
+        pick = np.where(a <= 0.0, 0, pick)
+        out[..., comp] = (pick | (np.signbit(x) << 7)).astype(np.uint8)
+    return out, scale
+
+
+def from_e4m3(codes, scale):
+    """The complex64 values an FP8 chunk stores: decoded x scale in float32."""
+    re = E4M3[codes[..., 0]].astype(np.float32) * scale[..., None]
+    im = E4M3[codes[..., 1]].astype(np.float32) * scale[..., None]
+    return (re + 1j * im).astype(np.complex64)
+
+
 def workload_names():
     return list(_WORKLOADS)
 
