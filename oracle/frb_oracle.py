@@ -23,6 +23,9 @@ Steps and the passages they follow (section / equation of the paper):
   O13 cross-baseline matching ..................... Sec. 2.4.1 (cross matching)
   PS  power-summation scheme ...................... Sec. 2.4.2
   CA  initial-phase / channel-delay extraction ..... Appendix A
+  R1-R4 refinement of a coarse peak: |G| at continuous SBD, MBD and rate
+      (Eq. 5 with the Eq. 4 rate term) and at a continuous DM (Eq. 1 without
+      the rounding of Eq. 2, frames interpolated), with its gradient
   H1  DM resolution ............................... Eq. 10
   H2  noise level ................................. Eq. 7
 
@@ -45,6 +48,11 @@ Readings where the paper is silent (each also listed in the design notes):
   * grouping: insertion orders, the overlap rule on closed frame intervals
     [k0, k0 + l - 1], the circular MBD mean and the open +-T/4 interval as in
     group_windows(); best member by normalised power.
+  * refinement (not in the paper, which grids every parameter): Eq. 2's
+    rounding is relaxed by Keys' cubic interpolation (a = -1/2) of each
+    channel's frames at the unrounded Eq. 1 shift plus a continuous arrival
+    offset t; samples outside the data are zero; the ascent runs in grid-cell
+    units with Adam moments.
 Units: MHz, ms, microseconds (so MHz * us = cycles), pc cm^-3; rate in s/s.
 """
 from __future__ import annotations
@@ -561,3 +569,155 @@ def dm_resolution(t_win_min_ms, f_low_mhz, f_high_mhz):
 def noise_level_jy(sefd1, sefd2, bandwidth_hz, t_s):
     """H2, Eq. 7: S_noise = sqrt(SEFD1 SEFD2 / (2 B T))."""
     return math.sqrt(sefd1 * sefd2 / (2.0 * bandwidth_hz * t_s))
+
+
+# ----------------------------------------------------------------------------
+# Refinement of a coarse peak (R1-R4): |G| as a function of continuous
+# (SBD, MBD, rate, DM, arrival offset) and its analytic gradient.
+# ----------------------------------------------------------------------------
+REFINE_PARAMS = ("sbd_us", "mbd_us", "rate", "dm", "t_frames")
+
+
+def keys_kernel(s):
+    """R1: Keys' cubic convolution kernel with a = -1/2 (Catmull-Rom):
+    phi(s) = 3/2 |s|^3 - 5/2 |s|^2 + 1 for |s| <= 1,
+    -1/2 |s|^3 + 5/2 |s|^2 - 4 |s| + 2 for 1 < |s| < 2, 0 beyond.
+    Interpolating, continuously differentiable, exact for quadratics.  It
+    relaxes the rounding of Eq. 2 so that the fringe amplitude becomes a
+    differentiable function of DM."""
+    a = np.abs(np.asarray(s, dtype=np.float64))
+    inner = 1.5 * a ** 3 - 2.5 * a ** 2 + 1.0
+    outer = -0.5 * a ** 3 + 2.5 * a ** 2 - 4.0 * a + 2.0
+    return np.where(a <= 1.0, inner, np.where(a < 2.0, outer, 0.0))
+
+
+def keys_kernel_deriv(s):
+    """d phi / d s of keys_kernel."""
+    s = np.asarray(s, dtype=np.float64)
+    a = np.abs(s)
+    inner = 4.5 * a ** 2 - 5.0 * a
+    outer = -1.5 * a ** 2 + 5.0 * a - 4.0
+    return np.sign(s) * np.where(a <= 1.0, inner, np.where(a < 2.0, outer, 0.0))
+
+
+def relaxed_offsets(dm, f0, n_chan, chan_bw, t_ap, k_dm=K_DM_DEFAULT):
+    """R2: the dispersion shift of Eq. 1 in frames, dt / t_ap, without the
+    rounding of Eq. 2, and its derivative with respect to DM ([N][J] each)."""
+    f = channel_sky_freq(f0, n_chan, chan_bw)
+    fr = ref_freq_dm(f0, n_chan, chan_bw)
+    dxd = k_dm * (1.0 / (f * f) - 1.0 / (fr * fr)) / t_ap
+    return dm * dxd, dxd
+
+
+def interpolated_frames(Vb, pos):
+    """R1 applied to every channel: the value at the continuous frame position
+    pos[n, j] of channel (n, j) of Vb [N][J][K], as sum_i V[n, j, i] phi(pos - i)
+    over the four samples i = floor(pos) - 1 .. floor(pos) + 2 (samples outside
+    the data count as zero), and its derivative with respect to pos."""
+    N, J, K = Vb.shape
+    base = np.floor(pos).astype(np.int64)
+    nn, jj = np.meshgrid(np.arange(N), np.arange(J), indexing="ij")
+    val = np.zeros((N, J), dtype=np.complex128)
+    der = np.zeros((N, J), dtype=np.complex128)
+    for m in range(-1, 3):
+        i = base + m
+        ok = (i >= 0) & (i < K)
+        v = np.where(ok, Vb[nn, jj, np.clip(i, 0, K - 1)], 0.0)
+        val += v * keys_kernel(pos - i)
+        der += v * keys_kernel_deriv(pos - i)
+    return val, der
+
+
+def relaxed_fringe(Vb, layout, search, cal, k0, l, theta, k_dm=K_DM_DEFAULT):
+    """R3: G(theta) for one segment of one baseline, theta = (SBD us, MBD us,
+    rate, DM, t frames):
+        G = sum_{n, j >= 1} cal[n,j] exp(-i 2 pi (f_j tau_s + (f0^n - f0^0) tau_m))
+              sum_u exp(-i 2 pi f0^n rho t_ap (u - (l-1)/2)) V~[n, j, k0 + t + x_nj(DM) + u]
+    -- Eq. 5 with the rate term of Eq. 4 (as in O5-O7) at continuous delays
+    and rate, and the dedispersed frame of Eq. 3 taken at the unrounded Eq. 1
+    shift plus an arrival offset t, interpolated by R1.  Returns G and the
+    five partial derivatives dG/dtheta_i (complex)."""
+    tau_s, tau_m, rho, dm, t = (float(v) for v in theta)
+    f0 = np.asarray(layout["if_freq_mhz"], dtype=np.float64)
+    J, df, t_ap = layout["n_chan"], layout["chan_bw_mhz"], layout["t_ap_ms"]
+    x, dxd = relaxed_offsets(dm, f0, J, df, t_ap, k_dm)
+    fj = np.arange(J, dtype=np.float64) * df
+    # phase of Eq. 5 at continuous delays; the j = 0 point is left out (Sec. 2.3)
+    e = cal * np.exp(-1j * TWO_PI * (fj[None, :] * tau_s + (f0 - f0[0])[:, None] * tau_m))
+    e[:, 0] = 0.0
+    S0 = np.zeros(e.shape, dtype=np.complex128)   # sum_u r V~
+    S1 = np.zeros(e.shape, dtype=np.complex128)   # sum_u d(r)/d(rho) V~
+    S2 = np.zeros(e.shape, dtype=np.complex128)   # sum_u r dV~/dpos
+    for u in range(l):
+        # rate phasor of Eq. 4 for frame u (f0 in MHz, t_ap in ms: factor 1e3)
+        w_rate = TWO_PI * 1e3 * f0 * t_ap * (u - (l - 1) / 2.0)
+        r = np.exp(-1j * rho * w_rate)[:, None]
+        val, der = interpolated_frames(Vb, k0 + t + x + u)
+        S0 += r * val
+        S1 += (-1j * w_rate)[:, None] * r * val
+        S2 += r * der
+    term = e * S0
+    G = term.sum()
+    dG = np.array([
+        np.sum(-1j * TWO_PI * fj[None, :] * term),
+        np.sum(-1j * TWO_PI * (f0 - f0[0])[:, None] * term),
+        np.sum(e * S1),
+        np.sum(e * S2 * dxd),
+        np.sum(e * S2),
+    ])
+    return G, dG
+
+
+def relaxed_power_grad(G, dG):
+    """R4: P = |G| and dP/dtheta = Re(conj(G) dG/dtheta) / |G|."""
+    P = abs(G)
+    if P == 0.0:
+        return 0.0, np.zeros(len(dG))
+    return P, np.real(np.conj(G) * dG) / P
+
+
+def refine_cells(layout, search):
+    """Grid cell of each refined parameter: SBD and MBD grid steps, the rate
+    step (0 when the grid has one rate: the rate is then held), the DM step,
+    one frame for the arrival offset."""
+    g = build_grids(layout, search)
+    J, df = layout["n_chan"], layout["chan_bw_mhz"]
+    sbd_cell = 1.0 / (search["sbd_pad"] * J * df)
+    mbd_cell = g["tau_m"][1] - g["tau_m"][0] if len(g["tau_m"]) > 1 else g["t_amb"]
+    rate_cell = g["rate_step"] if search["n_rate"] > 1 else 0.0
+    return np.array([sbd_cell, mbd_cell, rate_cell, search["dm_step"], 1.0])
+
+
+def coarse_theta(layout, search, d, r, s, m):
+    """The grid point of a coarse peak as a refinement start: (tau_s[s],
+    tau_m[m], rho[r], DM_d, 0)."""
+    g = build_grids(layout, search)
+    return np.array([g["tau_s"][s], g["tau_m"][m], g["rates"][r], g["dms"][d], 0.0])
+
+
+def adam_ascent(fn, theta0, cells, steps=20, lr0=0.25, decay=0.8, b1=0.5, b2=0.9, eps=1e-8):
+    """Gradient ascent of P(theta) in grid-cell units z = (theta - theta0) / cell
+    with Adam moments (Kingma & Ba 2015: m <- b1 m + (1-b1) g,
+    v <- b2 v + (1-b2) g^2, step lr_k m^ / (sqrt(v^) + eps), bias-corrected),
+    lr_k = lr0 decay^k.  Parameters whose cell is 0 are held.  fn(theta)
+    returns (P, dP/dtheta).  Returns the final theta and the P history."""
+    theta0 = np.asarray(theta0, dtype=np.float64)
+    cells = np.asarray(cells, dtype=np.float64)
+    live = cells > 0
+    z = np.zeros_like(theta0)
+    m = np.zeros_like(theta0)
+    v = np.zeros_like(theta0)
+    hist = []
+    for k in range(steps):
+        theta = theta0 + z * cells
+        P, g = fn(theta)
+        hist.append(P)
+        gz = np.where(live, g * cells, 0.0)
+        m = b1 * m + (1 - b1) * gz
+        v = b2 * v + (1 - b2) * gz * gz
+        mh = m / (1 - b1 ** (k + 1))
+        vh = v / (1 - b2 ** (k + 1))
+        z = z + lr0 * decay ** k * mh / (np.sqrt(vh) + eps)
+    theta = theta0 + z * cells
+    hist.append(fn(theta)[0])
+    return theta, np.array(hist)
