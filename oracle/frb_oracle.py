@@ -23,7 +23,7 @@ Steps and the passages they follow (section / equation of the paper):
   O13 cross-baseline matching ..................... Sec. 2.4.1 (cross matching)
   PS  power-summation scheme ...................... Sec. 2.4.2
   CA  initial-phase / channel-delay extraction ..... Appendix A
-  R1-R4 refinement of a coarse peak: |G| at continuous SBD, MBD and rate
+  R1-R5 refinement of a coarse peak: |G| at continuous SBD, MBD and rate
       (Eq. 5 with the Eq. 4 rate term) and at a continuous DM (Eq. 1 without
       the rounding of Eq. 2, frames interpolated), with its gradient
   H1  DM resolution ............................... Eq. 10
@@ -52,7 +52,7 @@ Readings where the paper is silent (each also listed in the design notes):
     rounding is relaxed by Keys' cubic interpolation (a = -1/2) of each
     channel's frames at the unrounded Eq. 1 shift plus a continuous arrival
     offset t; samples outside the data are zero; the ascent runs in grid-cell
-    units with Adam moments.
+    units with a diagonal Newton step (grid cells, DM decorrelated from t).
 Units: MHz, ms, microseconds (so MHz * us = cycles), pc cm^-3; rate in s/s.
 """
 from __future__ import annotations
@@ -600,6 +600,12 @@ def keys_kernel_deriv(s):
     return np.sign(s) * np.where(a <= 1.0, inner, np.where(a < 2.0, outer, 0.0))
 
 
+def keys_kernel_deriv2(s):
+    """d^2 phi / d s^2 of keys_kernel (piecewise linear, even)."""
+    a = np.abs(np.asarray(s, dtype=np.float64))
+    return np.where(a <= 1.0, 9.0 * a - 5.0, np.where(a < 2.0, -3.0 * a + 5.0, 0.0))
+
+
 def relaxed_offsets(dm, f0, n_chan, chan_bw, t_ap, k_dm=K_DM_DEFAULT):
     """R2: the dispersion shift of Eq. 1 in frames, dt / t_ap, without the
     rounding of Eq. 2, and its derivative with respect to DM ([N][J] each)."""
@@ -613,19 +619,22 @@ def interpolated_frames(Vb, pos):
     """R1 applied to every channel: the value at the continuous frame position
     pos[n, j] of channel (n, j) of Vb [N][J][K], as sum_i V[n, j, i] phi(pos - i)
     over the four samples i = floor(pos) - 1 .. floor(pos) + 2 (samples outside
-    the data count as zero), and its derivative with respect to pos."""
+    the data count as zero), and its first and second derivatives with
+    respect to pos."""
     N, J, K = Vb.shape
     base = np.floor(pos).astype(np.int64)
     nn, jj = np.meshgrid(np.arange(N), np.arange(J), indexing="ij")
     val = np.zeros((N, J), dtype=np.complex128)
     der = np.zeros((N, J), dtype=np.complex128)
+    der2 = np.zeros((N, J), dtype=np.complex128)
     for m in range(-1, 3):
         i = base + m
         ok = (i >= 0) & (i < K)
         v = np.where(ok, Vb[nn, jj, np.clip(i, 0, K - 1)], 0.0)
         val += v * keys_kernel(pos - i)
         der += v * keys_kernel_deriv(pos - i)
-    return val, der
+        der2 += v * keys_kernel_deriv2(pos - i)
+    return val, der, der2
 
 
 def relaxed_fringe(Vb, layout, search, cal, k0, l, theta, k_dm=K_DM_DEFAULT):
@@ -635,8 +644,10 @@ def relaxed_fringe(Vb, layout, search, cal, k0, l, theta, k_dm=K_DM_DEFAULT):
               sum_u exp(-i 2 pi f0^n rho t_ap (u - (l-1)/2)) V~[n, j, k0 + t + x_nj(DM) + u]
     -- Eq. 5 with the rate term of Eq. 4 (as in O5-O7) at continuous delays
     and rate, and the dedispersed frame of Eq. 3 taken at the unrounded Eq. 1
-    shift plus an arrival offset t, interpolated by R1.  Returns G and the
-    five partial derivatives dG/dtheta_i (complex)."""
+    shift plus an arrival offset t, interpolated by R1.  Returns G, the five
+    partial derivatives dG/dtheta_i and the second derivatives
+    d2G[i] = d^2 G / d theta_i^2 (i = 0..4) with d2G[5] = d^2 G / d DM d t
+    (complex)."""
     tau_s, tau_m, rho, dm, t = (float(v) for v in theta)
     f0 = np.asarray(layout["if_freq_mhz"], dtype=np.float64)
     J, df, t_ap = layout["n_chan"], layout["chan_bw_mhz"], layout["t_ap_ms"]
@@ -647,33 +658,59 @@ def relaxed_fringe(Vb, layout, search, cal, k0, l, theta, k_dm=K_DM_DEFAULT):
     e[:, 0] = 0.0
     S0 = np.zeros(e.shape, dtype=np.complex128)   # sum_u r V~
     S1 = np.zeros(e.shape, dtype=np.complex128)   # sum_u d(r)/d(rho) V~
+    S11 = np.zeros(e.shape, dtype=np.complex128)  # sum_u d2(r)/d(rho)2 V~
     S2 = np.zeros(e.shape, dtype=np.complex128)   # sum_u r dV~/dpos
+    S3 = np.zeros(e.shape, dtype=np.complex128)   # sum_u r d2V~/dpos2
     for u in range(l):
         # rate phasor of Eq. 4 for frame u (f0 in MHz, t_ap in ms: factor 1e3)
         w_rate = TWO_PI * 1e3 * f0 * t_ap * (u - (l - 1) / 2.0)
         r = np.exp(-1j * rho * w_rate)[:, None]
-        val, der = interpolated_frames(Vb, k0 + t + x + u)
+        val, der, der2 = interpolated_frames(Vb, k0 + t + x + u)
         S0 += r * val
         S1 += (-1j * w_rate)[:, None] * r * val
+        S11 += (-1j * w_rate)[:, None] ** 2 * r * val
         S2 += r * der
+        S3 += r * der2
     term = e * S0
     G = term.sum()
+    ws = -1j * TWO_PI * fj[None, :]
+    wm = -1j * TWO_PI * (f0 - f0[0])[:, None]
     dG = np.array([
-        np.sum(-1j * TWO_PI * fj[None, :] * term),
-        np.sum(-1j * TWO_PI * (f0 - f0[0])[:, None] * term),
+        np.sum(ws * term),
+        np.sum(wm * term),
         np.sum(e * S1),
         np.sum(e * S2 * dxd),
         np.sum(e * S2),
     ])
-    return G, dG
+    d2G = np.array([
+        np.sum(ws * ws * term),
+        np.sum(wm * wm * term),
+        np.sum(e * S11),
+        np.sum(e * S3 * dxd * dxd),
+        np.sum(e * S3),
+        np.sum(e * S3 * dxd),
+    ])
+    return G, dG, d2G
 
 
-def relaxed_power_grad(G, dG):
-    """R4: P = |G| and dP/dtheta = Re(conj(G) dG/dtheta) / |G|."""
+def relaxed_power_grad(G, dG, d2G=None):
+    """R4: P = |G|, dP/dtheta_a = Re(conj(G) G_a) / P and (with d2G) the
+    second derivatives
+    P_ab = [Re(conj(G_a) G_b) + Re(conj(G) G_ab)] / P - P_a P_b / P
+    for the five diagonal entries and (DM, t): returns (P, grad[5]) or
+    (P, grad[5], H[6])."""
     P = abs(G)
     if P == 0.0:
-        return 0.0, np.zeros(len(dG))
-    return P, np.real(np.conj(G) * dG) / P
+        z = np.zeros(len(dG))
+        return (0.0, z) if d2G is None else (0.0, z, np.zeros(6))
+    g = np.real(np.conj(G) * dG) / P
+    if d2G is None:
+        return P, g
+    H = np.empty(6)
+    for i in range(5):
+        H[i] = (abs(dG[i]) ** 2 + np.real(np.conj(G) * d2G[i])) / P - g[i] * g[i] / P
+    H[5] = (np.real(np.conj(dG[3]) * dG[4]) + np.real(np.conj(G) * d2G[5])) / P - g[3] * g[4] / P
+    return P, g, H
 
 
 def refine_cells(layout, search):
@@ -695,29 +732,46 @@ def coarse_theta(layout, search, d, r, s, m):
     return np.array([g["tau_s"][s], g["tau_m"][m], g["rates"][r], g["dms"][d], 0.0])
 
 
-def adam_ascent(fn, theta0, cells, steps=20, lr0=0.25, decay=0.8, b1=0.5, b2=0.9, eps=1e-8):
-    """Gradient ascent of P(theta) in grid-cell units z = (theta - theta0) / cell
-    with Adam moments (Kingma & Ba 2015: m <- b1 m + (1-b1) g,
-    v <- b2 v + (1-b2) g^2, step lr_k m^ / (sqrt(v^) + eps), bias-corrected),
-    lr_k = lr0 decay^k.  Parameters whose cell is 0 are held.  fn(theta)
-    returns (P, dP/dtheta).  Returns the final theta and the P history."""
+def mean_dm_shift(layout, k_dm=K_DM_DEFAULT):
+    """Mean over the fitted points (j >= 1) of d x / d DM (frames per pc cm^-3):
+    the arrival offset that a DM change moves on average."""
+    f0 = np.asarray(layout["if_freq_mhz"], dtype=np.float64)
+    _, dxd = relaxed_offsets(1.0, f0, layout["n_chan"], layout["chan_bw_mhz"], layout["t_ap_ms"], k_dm)
+    return float(dxd[:, 1:].mean())
+
+
+def newton_ascent(fn, theta0, cells, xbar, steps=20, max_step=0.5):
+    """R5: ascent of P(theta) from a coarse grid point.  Coordinates z in
+    grid cells, theta = theta0 + cells * (A z) with A the identity except
+    that a DM step moves the arrival offset by -xbar per unit DM (the time
+    reference follows the mean dispersion shift, which decorrelates DM from
+    t).  Each step moves every live coordinate by -g_i / H_ii (gradient over
+    curvature of P in z) where H_ii < 0, else by max_step in the gradient's
+    direction, clipped to +-max_step; coordinates whose cell is 0 are held.
+    fn(theta) returns (P, grad[5], H[6]).  Returns (theta, P history)."""
     theta0 = np.asarray(theta0, dtype=np.float64)
     cells = np.asarray(cells, dtype=np.float64)
     live = cells > 0
-    z = np.zeros_like(theta0)
-    m = np.zeros_like(theta0)
-    v = np.zeros_like(theta0)
+    a = -xbar * cells[3] / cells[4] if cells[4] > 0 else 0.0
+    z = np.zeros(5)
     hist = []
-    for k in range(steps):
-        theta = theta0 + z * cells
-        P, g = fn(theta)
+
+    def theta_of(z):
+        dz = z.copy()
+        dz[4] += a * z[3]
+        return theta0 + cells * dz
+
+    for _ in range(steps):
+        P, g, H = fn(theta_of(z))
         hist.append(P)
-        gz = np.where(live, g * cells, 0.0)
-        m = b1 * m + (1 - b1) * gz
-        v = b2 * v + (1 - b2) * gz * gz
-        mh = m / (1 - b1 ** (k + 1))
-        vh = v / (1 - b2 ** (k + 1))
-        z = z + lr0 * decay ** k * mh / (np.sqrt(vh) + eps)
-    theta = theta0 + z * cells
+        gc = g * cells
+        gz = gc.copy()
+        gz[3] += a * gc[4]
+        hz = np.array([H[i] * cells[i] ** 2 for i in range(5)])
+        hz[3] = (H[3] * cells[3] ** 2 + 2 * a * H[5] * cells[3] * cells[4]
+                 + a * a * H[4] * cells[4] ** 2)
+        step = np.where(hz < 0, -gz / np.where(hz < 0, hz, -1.0), max_step * np.sign(gz))
+        z = z + np.where(live, np.clip(step, -max_step, max_step), 0.0)
+    theta = theta_of(z)
     hist.append(fn(theta)[0])
     return theta, np.array(hist)

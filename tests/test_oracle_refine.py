@@ -1,0 +1,226 @@
+"""CPU pins of the oracle's refinement functions (R1-R5): the interpolation
+kernel's defining properties, the relaxed fringe amplitude against the
+coarse oracle and closed forms, analytic derivatives against central
+differences, and recovery of injected parameters."""
+import math
+
+import numpy as np
+import pytest
+
+from oracle import frb_oracle as O
+from paper_1801_02391_amd import workloads as W
+
+
+def _layout(N=4, J=16, df=1.0, t_ap=1.0, K=120, spacing=32.0):
+    f0 = [3000.0 + spacing * n * (n + 1) / 2 for n in range(N)]
+    return dict(if_freq_mhz=f0, n_if=N, n_chan=J, chan_bw_mhz=df, t_ap_ms=t_ap, n_frames=K)
+
+
+def _search(**kw):
+    s = dict(dm_lo=0.0, dm_step=20.0, n_dm=4, k_dm=4.149e6, sbd_pad=4, n_mbd=64, mbd_step_us=0.0,
+             f_ref_fit_mhz=float("nan"), n_rate=3, rate_step=0.0, windows=[4, 8])
+    s.update(kw)
+    return s
+
+
+def _noise(rng, N, J, K):
+    return (rng.standard_normal((N, J, K)) + 1j * rng.standard_normal((N, J, K))) / math.sqrt(2)
+
+
+# ---------------------------------------------------------------- R1 kernel
+def test_keys_kernel_interpolates_and_reproduces_quadratics():
+    assert O.keys_kernel(0.0) == 1.0
+    for k in (-2, -1, 1, 2, 3):
+        assert O.keys_kernel(float(k)) == 0.0
+    rng = np.random.default_rng(1)
+    ks = np.arange(-3, 4)
+    for x in rng.uniform(-0.5, 0.5, 20):
+        w = O.keys_kernel(x - ks)
+        assert w.sum() == pytest.approx(1.0, abs=1e-14)          # partition of unity
+        a, b, c = rng.standard_normal(3)
+        p = a + b * ks + c * ks ** 2                               # quadratics are exact
+        assert np.dot(w, p) == pytest.approx(a + b * x + c * x * x, abs=1e-12)
+        # derivatives of the interpolant are the derivatives of the quadratic
+        assert np.dot(O.keys_kernel_deriv(x - ks), p) == pytest.approx(b + 2 * c * x, abs=1e-12)
+        assert np.dot(O.keys_kernel_deriv2(x - ks), p) == pytest.approx(2 * c, abs=1e-11)
+
+
+def test_keys_kernel_derivatives_match_central_differences():
+    s = np.linspace(-2.4, 2.4, 97) + 0.013
+    h = 1e-6
+    fd1 = (O.keys_kernel(s + h) - O.keys_kernel(s - h)) / (2 * h)
+    fd2 = (O.keys_kernel_deriv(s + h) - O.keys_kernel_deriv(s - h)) / (2 * h)
+    assert np.allclose(O.keys_kernel_deriv(s), fd1, atol=1e-8)
+    assert np.allclose(O.keys_kernel_deriv2(s), fd2, atol=1e-6)
+    # continuously differentiable across the knots
+    for k in (-2.0, -1.0, 0.0, 1.0, 2.0):
+        assert O.keys_kernel_deriv(k - 1e-12) == pytest.approx(O.keys_kernel_deriv(k + 1e-12), abs=1e-9)
+
+
+# ------------------------------------------------------- R3 against the coarse oracle
+def test_relaxed_equals_coarse_search_at_zero_dm_on_the_grid():
+    """At DM = 0 and t = 0 the relaxed frames are the samples themselves, so
+    at grid delays and rate G equals the coarse oracle's cell (O5-O7)."""
+    lay, s = _layout(), _search()
+    rng = np.random.default_rng(2)
+    N, J, K = 4, 16, 120
+    Vb = _noise(rng, N, J, K)
+    cal = O.calibration_phasor(J, 1.0, rng.uniform(-0.01, 0.01, N), rng.uniform(-1, 1, N))
+    g = O.build_grids(lay, s)
+    l, k0 = 8, 37
+    rph = O.rate_phasor(g["rates"], g["f0"], l, g["t_ap"])
+    Y = O.segment_sums(Vb, np.zeros((N, J), dtype=np.int64), [k0], l, rph, cal)
+    Gc = O.fringe_matrix(Y, g["e_sbd"], g["e_mbd"])[0]                 # [R][PJ][M]
+    for (r, si, m) in [(0, 3, 5), (1, 40, 63), (2, 17, 0), (1, 32, 32)]:
+        th = [g["tau_s"][si], g["tau_m"][m], g["rates"][r], 0.0, 0.0]
+        G, _, _ = O.relaxed_fringe(Vb, lay, s, cal, k0, l, th)
+        assert G == pytest.approx(Gc[r, si, m], rel=1e-12, abs=1e-12)
+
+
+def test_time_constant_data_make_dm_and_offset_irrelevant():
+    """Frames constant in time: interpolation returns the constant (partition
+    of unity) at any DM and offset, so G equals the DM-0 value."""
+    lay, s = _layout(), _search()
+    rng = np.random.default_rng(3)
+    N, J, K = 4, 16, 120
+    c = _noise(rng, N, J, 1)
+    Vb = np.repeat(c, K, axis=2)
+    cal = np.ones((N, J), complex)
+    th = np.array([0.013, 0.0021, 0.0, 0.0, 0.0])
+    G0, _, _ = O.relaxed_fringe(Vb, lay, s, cal, 40, 8, th)
+    for dm, t in [(37.3, 0.41), (55.0, -1.7), (12.25, 0.0)]:
+        th2 = th.copy()
+        th2[3], th2[4] = dm, t
+        G, dG, _ = O.relaxed_fringe(Vb, lay, s, cal, 40, 8, th2)
+        assert G == pytest.approx(G0, rel=1e-12)
+        assert abs(dG[3]) < 1e-9 * abs(G) and abs(dG[4]) < 1e-9 * abs(G)
+
+
+def test_off_grid_tone_is_a_product_of_dirichlet_kernels():
+    """A pure delay tau: |G(tau_s, tau_m)| = A l |sum_{j>=1} z_s^j| |sum_n z_m^{q_n}|
+    with the first sum in its geometric closed form."""
+    lay, s = _layout(), _search()
+    N, J, K, df = 4, 16, 120, 1.0
+    A, tau, l = 0.7, 0.0437, 6
+    f = O.channel_sky_freq(lay["if_freq_mhz"], J, df)
+    Vb = np.repeat((A * np.exp(2j * np.pi * f * tau))[:, :, None], K, axis=2)
+    cal = np.ones((N, J), complex)
+    f0 = np.asarray(lay["if_freq_mhz"])
+    for ts, tm in [(0.0, 0.0), (0.05, 0.04), (-0.2, 0.1), (0.0437, 0.0437)]:
+        G, _, _ = O.relaxed_fringe(Vb, lay, s, cal, 30, l, [ts, tm, 0.0, 0.0, 0.0])
+        z = np.exp(2j * np.pi * df * (tau - ts))
+        dj = z * (1 - z ** (J - 1)) / (1 - z) if abs(1 - z) > 1e-12 else J - 1
+        dn = np.sum(np.exp(2j * np.pi * (f0 - f0[0]) * (tau - tm)))
+        assert abs(G) == pytest.approx(A * l * abs(dj) * abs(dn), rel=1e-10)
+
+
+def test_rate_tone_is_fully_coherent_at_its_rate_and_window_centre_delay():
+    """Frames rotating at a delay rate rho*: at rho = rho* the per-IF residual
+    phase is 2 pi f0^n delta with delta = 1e3 rho* t_ap (k0 + (l-1)/2) us, so
+    |G| = A l N (J-1) at tau_m = delta, and the gradient vanishes there."""
+    lay, s = _layout(K=200), _search()
+    N, J, K = 4, 16, 200
+    A, rho, l, k0 = 0.5, 3.1e-8, 8, 60
+    f0 = np.asarray(lay["if_freq_mhz"])
+    k = np.arange(K)
+    Vb = A * np.exp(2j * np.pi * 1e3 * f0[:, None, None] * rho * 1.0 * k[None, None, :]) * np.ones((N, J, 1))
+    delta = 1e3 * rho * 1.0 * (k0 + (l - 1) / 2)
+    cal = np.ones((N, J), complex)
+    G, dG, _ = O.relaxed_fringe(Vb, lay, s, cal, k0, l, [0.0, delta, rho, 0.0, 0.0])
+    assert abs(G) == pytest.approx(A * l * N * (J - 1), rel=1e-12)
+    P, g = O.relaxed_power_grad(G, dG)
+    assert abs(g[1]) < 1e-9 * P and abs(g[2]) * 1e-8 < 1e-9 * P
+
+
+# ------------------------------------------------------- R4 derivatives
+def test_gradient_and_curvature_match_central_differences():
+    lay, s = _layout(), _search()
+    rng = np.random.default_rng(5)
+    N, J, K = 4, 16, 120
+    Vb = _noise(rng, N, J, K)
+    cal = O.calibration_phasor(J, 1.0, rng.uniform(-0.01, 0.01, N), rng.uniform(-1, 1, N))
+    cells = O.refine_cells(lay, s)
+    for trial in range(3):
+        th = np.array([rng.uniform(-0.3, 0.3), rng.uniform(-0.01, 0.01), rng.uniform(-1, 1) * cells[2],
+                       rng.uniform(0, 60), rng.uniform(-2, 2)])
+        G, dG, d2G = O.relaxed_fringe(Vb, lay, s, cal, 40, 8, th)
+        P, g, H = O.relaxed_power_grad(G, dG, d2G)
+        for i in range(5):
+            h = 1e-5 * cells[i]
+            e = np.zeros(5)
+            e[i] = h
+            Pp, gp = O.relaxed_power_grad(*O.relaxed_fringe(Vb, lay, s, cal, 40, 8, th + e)[:2])
+            Pm, gm = O.relaxed_power_grad(*O.relaxed_fringe(Vb, lay, s, cal, 40, 8, th - e)[:2])
+            scale = P / cells[i]
+            assert g[i] == pytest.approx((Pp - Pm) / (2 * h), abs=1e-6 * scale)
+            assert H[i] == pytest.approx((gp[i] - gm[i]) / (2 * h), abs=1e-5 * scale / cells[i])
+            if i == 3:
+                assert H[5] == pytest.approx((gp[4] - gm[4]) / (2 * h), abs=1e-5 * P / (cells[3] * cells[4]))
+
+
+# ------------------------------------------------------- recovery of the truth
+def test_relaxed_dm_peaks_at_the_true_dm_of_a_smooth_pulse():
+    """A noise-free Gaussian-profile pulse (sigma 2.5 frames) dispersed by an
+    off-grid DM: the ascent from the nearest grid point lands on that DM
+    (within 0.02 DM steps) with the window centred on the pulse."""
+    lay, s = _layout(N=6, J=16, K=260, spacing=16.0), _search(dm_step=40.0, n_dm=8, n_rate=1, windows=[8])
+    N, J, K = 6, 16, 260
+    dm_true, t0, sig, A = 177.7, 120.3, 2.5, 1.0
+    x, _ = O.relaxed_offsets(dm_true, lay["if_freq_mhz"], J, 1.0, 1.0)
+    k = np.arange(K)
+    Vb = A * np.exp(-0.5 * ((k[None, None, :] - (t0 + x)[:, :, None]) / sig) ** 2).astype(np.complex128)
+    cal = np.ones((N, J), complex)
+    l, k0 = 8, 116
+    cells = O.refine_cells(lay, s)
+    xbar = O.mean_dm_shift(lay)
+    fn = lambda th: O.relaxed_power_grad(*O.relaxed_fringe(Vb, lay, s, cal, k0, l, th))
+    th0 = np.array([0.0, 0.0, 0.0, 160.0, 0.0])
+    th, hist = O.newton_ascent(fn, th0, cells, xbar, steps=20)
+    assert hist[-1] >= hist[0]
+    assert abs(th[3] - dm_true) / cells[3] < 0.02
+    assert abs(th[4] - (t0 - k0 - (l - 1) / 2)) < 0.05
+    assert abs(th[0]) < 1e-6 and abs(th[1]) < 1e-6
+
+
+@pytest.mark.parametrize("seed", [0, 1, 4])
+def test_ascent_recovers_noise_free_boxcar_pulse_within_0p05_cell(seed):
+    """The workload's boxcar pulse (fractional AP coverage), noise-free, window
+    equal to the pulse width: from the best coarse cell the 20-step ascent
+    recovers SBD, MBD (mod the ambiguity), rate, DM and the arrival AP within
+    0.05 grid cell."""
+    rng = np.random.default_rng(100 + seed)
+    f0 = [3000.0 + 32.0 * n for n in range(8)]
+    dm, w = float(rng.uniform(200, 800)), int(rng.integers(2, 7))
+    tau, t0 = float(rng.uniform(-0.4, 0.4)), float(rng.uniform(30, 60))
+    step = 15.625
+    lo = max(0, int(dm / step) - 2)
+    wl = W.custom_workload(if_freq_mhz=f0, n_chan=32, chan_bw_mhz=1.0, t_ap_ms=1.0, n_frames=260,
+                           config_id=140 + seed,
+                           search=dict(dm_lo=lo * step, dm_step=step, n_dm=5, sbd_pad=4, n_mbd=256,
+                                       n_rate=3, windows=[w]),
+                           signal=dict(noise=False, pulses=dict(kind="fixed", list=[
+                               dict(t0_ms=t0, dm=dm, width_ms=float(w), snr=30.0, delay_us=tau)])))
+    V, _ = W.generate(wl)
+    lay, s = wl["layout"], wl["search"]
+    Vb = V[0].astype(np.complex128)
+    g = O.build_grids(lay, s)
+    cal = np.ones((8, 32), complex)
+    best = None
+    for d in range(s["n_dm"]):
+        P, I, _ = O.search_row(Vb, g, cal, d, 0)
+        q = int(np.argmax(P))
+        if best is None or P[q] > best[0]:
+            best = (P[q], d, q, int(I[q]))
+    _, d, q, idx = best
+    l, h, _ = g["segs"][0]
+    r, sb, m = O.unpack_index(idx, 4 * 32, 256)
+    k0 = q * h
+    th0 = O.coarse_theta(lay, s, d, r, sb, m)
+    cells = O.refine_cells(lay, s)
+    fn = lambda th: O.relaxed_power_grad(*O.relaxed_fringe(Vb, lay, s, cal, k0, l, th))
+    th, hist = O.newton_ascent(fn, th0, cells, O.mean_dm_shift(lay), steps=20)
+    T = g["t_amb"]
+    err = (th - np.array([tau, tau, 0.0, dm, t0 - k0])) / cells
+    err[1] = ((th[1] - tau + T / 2) % T - T / 2) / cells[1]
+    assert np.all(np.abs(err) < 0.05), err
+    assert hist[-1] >= hist[0]
