@@ -285,6 +285,66 @@ frbx_status frbx_power_sum(frbx_ctx *ctx, const int32_t *baselines, int32_t n_bl
 frbx_status frbx_calibrate(frbx_ctx *ctx, int32_t baseline, int64_t k0, int32_t len,
                            double *tau0_us, double *phi0_rad);
 
+/* ---- Refinement of coarse peaks ------------------------------------------
+ * |G| of one segment as a function of continuous parameters
+ *   theta = (SBD tau_s [us], MBD tau_m [us], delay rate rho [s/s],
+ *            DM [pc cm^-3], arrival offset t [APs]):
+ *   G = sum_{n, j >= 1} C_b(n,j) exp(-2 pi i (f_j tau_s + (f0^n - f0^0) tau_m))
+ *         sum_{u<l} exp(-2 pi i 1e3 f0^n rho t_ap (u - (l-1)/2))
+ *                   V~_b(n, j, k0 + t + x_nj(DM) + u)
+ * -- Eq. 5 with the rate term of Eq. 4 at continuous delays and rate, and
+ * the frames of Eq. 3 taken at the unrounded Eq. 1 shift
+ * x_nj(DM) = k_DM DM (f^-2 - f_ref^-2) / t_ap plus t, where V~ is Keys'
+ * cubic interpolation (a = -1/2) of the frames of the channel (frames outside
+ * the data count as zero).  The relaxation replaces the rounding of Eq. 2,
+ * whose gradient in DM is zero; at DM = 0, t = 0 and grid delays and rate
+ * P = |G| equals the coarse search's cell.  Sums in float32, phase
+ * arguments in float64.  Needs input loaded with frbx_load /
+ * frbx_load_f16 (not a stream); the input must stay resident.
+ *
+ * The ascent (frbx_refine_run) moves, per step, every coordinate in grid
+ * cells z by -g/H (gradient over curvature of P in z) where H < 0, else by
+ * max_step = 0.5 cell along the gradient, clipped to +-0.5 cell.  Cells:
+ * SBD 1/(P J chan_bw), MBD the MBD grid step, rate the rate step (held when
+ * the grid has one rate), DM the DM step, t one AP.  A DM step moves t by
+ * -xbar per unit DM (xbar = mean of dx/dDM over the fitted points), which
+ * decorrelates DM from the arrival offset. */
+
+/* The n_max crossings of the last frbx_run with the highest normalised
+ * power (ties: baseline, DM trial, window, segment ascending), as
+ * frbx_candidate records; cap = 0 is a size query (E_RANGE). */
+frbx_status frbx_top_peaks(const frbx_ctx *ctx, int64_t n_max, frbx_candidate *out, int64_t cap,
+                           int64_t *n);
+
+/* Start a refinement of n peaks (host records: baseline, dm_index,
+ * window_len, k0, rate_idx, sbd_idx, mbd_idx are read).  The start point of
+ * each is its grid cell (tau_s[sbd_idx], tau_m[mbd_idx], rho[rate_idx],
+ * DM[dm_index], 0); theta0 (host [n][5], may be NULL) receives it.  Device
+ * buffers for n peaks are held by the context until the next begin. */
+frbx_status frbx_refine_begin(frbx_ctx *ctx, const frbx_candidate *peaks, int64_t n, double *theta0);
+
+/* n_steps ascent steps on the device (one launch each), then P at the final
+ * parameters. */
+frbx_status frbx_refine_run(frbx_ctx *ctx, int32_t n_steps);
+
+/* Results of frbx_refine_run: theta host [n][5], power host [n] (either may
+ * be NULL); cap = 0 is a size query. */
+frbx_status frbx_refine_results(const frbx_ctx *ctx, double *theta, float *power, int64_t cap,
+                                int64_t *n);
+
+/* Forward, backward and curvature on the begun peaks, with device pointers
+ * on the context stream (the pieces of a torch.autograd.Function):
+ *   forward:   power[i] = P(theta_i)                      theta [n][5] f64, power [n] f32
+ *   backward:  grad_theta[i][k] = grad_power[i] dP/dtheta_k (theta_i)
+ *   curvature: curv[i][k] = d2P/dtheta_k^2 (k < 5), curv[i][5] = d2P/dDM dt */
+frbx_status frbx_refine_forward(frbx_ctx *ctx, const double *theta, float *power);
+frbx_status frbx_refine_backward(frbx_ctx *ctx, const double *theta, const float *grad_power,
+                                 double *grad_theta);
+frbx_status frbx_refine_curvature(frbx_ctx *ctx, const double *theta, double *curv);
+
+/* The ascent's grid cells [5] and xbar (host outputs, either may be NULL). */
+frbx_status frbx_refine_cells(frbx_ctx *ctx, double *cells, double *xbar);
+
 /* |G|^2 of every cell of one segment, [R][PJ][M] float32 into a device
  * buffer of the caller (for element-wise checks of the fringe transform;
  * needs a loaded context with valid grids). */
@@ -309,6 +369,10 @@ typedef struct {
                                  launches: every dedispersed spectrum written
                                  once, every channel's input span read once
                                  per group of DM trials */
+  double refine_ms;           /* refinement launches of the last
+                                 frbx_refine_run (timed like the others) */
+  int64_t n_refine;
+  int64_t refine_units;       /* peaks x launches */
 } frbx_timing;
 
 frbx_status frbx_set_timing(frbx_ctx *ctx, int enable);

@@ -119,6 +119,20 @@ struct frbx_ctx {
   std::vector<int64_t> next_q, push_first, push_nq;
   std::vector<frbx_candidate> stream_cross;
 
+  // refinement of coarse peaks
+  int64_t rn = 0;
+  frbx::RefineSeg *d_rseg = nullptr;
+  size_t rseg_cap = 0;
+  double *d_rtheta = nullptr;
+  size_t rtheta_cap = 0;
+  float *d_rpower = nullptr;
+  size_t rpower_cap = 0;
+  frbx::RefineChan *d_rchan = nullptr;
+  size_t rchan_cap = 0;
+  double rcells[5] = {0, 0, 0, 0, 0};
+  double rxbar = 0.0;
+  bool rdone = false, rbegun = false;
+
   // results
   bool have = false;
   std::vector<double> mean, sd;
@@ -164,6 +178,7 @@ struct frbx_ctx {
       if (sp.kind == 1)
         t.dedisperse_ms += ms, t.n_dedisperse++, t.dedisperse_units += sp.units, t.dedisperse_bytes += sp.bytes;
       if (sp.kind == 2) t.stats_ms += ms, t.n_stats++;
+      if (sp.kind == 3) t.refine_ms += ms, t.n_refine++, t.refine_units += sp.units;
     }
     last_timing = t;
     spans.clear();
@@ -195,6 +210,10 @@ struct frbx_ctx {
     dfree(d_cnt);
     dfree(d_cross);
     dfree(d_ncross);
+    dfree(d_rseg);
+    dfree(d_rtheta);
+    dfree(d_rpower);
+    dfree(d_rchan);
   }
 };
 
@@ -258,6 +277,7 @@ float2 cis_cycles(double x) {
 
 frbx_status prepare(frbx_ctx *c) {
   if (!c->dirty) return FRBX_OK;
+  c->rbegun = false;  // a refinement's cells and tables follow the grids
   const int N = c->N, J = c->J, NJ = N * J, D = c->n_dm;
   // AP offsets and segment layout (Eqs. 1-3)
   c->dk.assign(size_t(D) * NJ, 0);
@@ -1488,6 +1508,202 @@ frbx_status frbx_calibrate(frbx_ctx *c, int32_t b, int64_t k0, int32_t len, doub
     phi0[n] = std::atan2(acc.imag(), acc.real());
   }
   return FRBX_OK;
+}
+
+frbx_status frbx_top_peaks(const frbx_ctx *c, int64_t n_max, frbx_candidate *out, int64_t cap, int64_t *n) {
+  if (!c || !n || n_max < 0) return FRBX_E_INVAL;
+  if (!c->have || c->streaming) return FRBX_E_STATE;
+  std::vector<frbx_candidate> v(c->cross);
+  std::stable_sort(v.begin(), v.end(), [](const frbx_candidate &x, const frbx_candidate &y) {
+    if (x.power_norm != y.power_norm) return x.power_norm > y.power_norm;
+    if (x.baseline != y.baseline) return x.baseline < y.baseline;
+    if (x.dm_index != y.dm_index) return x.dm_index < y.dm_index;
+    if (x.window_index != y.window_index) return x.window_index < y.window_index;
+    return x.segment < y.segment;
+  });
+  if (int64_t(v.size()) > n_max) v.resize(size_t(n_max));
+  return copy_out(v, out, cap, n);
+}
+
+namespace {
+frbx::RefineArgs refine_args(const frbx_ctx *c) {
+  frbx::RefineArgs a{};
+  a.vis = c->d_vis;
+  a.in_f16 = c->vis_f16;
+  a.n_frames = c->K;
+  a.row_stride = c->K;
+  a.nj = c->N * c->J;
+  a.J = c->J;
+  a.chan = c->d_rchan;
+  a.cal = c->d_cal;
+  a.seg = c->d_rseg;
+  a.n = int32_t(c->rn);
+  for (int k = 0; k < 5; ++k) a.cells[k] = c->rcells[k];
+  a.dm_t = c->rcells[4] > 0 ? -c->rxbar * c->rcells[3] / c->rcells[4] : 0.0;
+  a.max_step = 0.5;
+  return a;
+}
+
+frbx_status refine_ready(frbx_ctx *c) {
+  if (!c) return FRBX_E_INVAL;
+  if (!c->rbegun || !c->d_rseg) return c->fail(FRBX_E_STATE, "no refinement begun");
+  if (c->dirty || !c->loaded || c->streaming)
+    return c->fail(FRBX_E_STATE, "grids or input changed since frbx_refine_begin");
+  if (hipSetDevice(c->device) != hipSuccess) return c->fail(FRBX_E_DEVICE, "hipSetDevice failed");
+  return FRBX_OK;
+}
+}  // namespace
+
+frbx_status frbx_refine_cells(frbx_ctx *c, double *cells, double *xbar) {
+  if (!c) return FRBX_E_INVAL;
+  frbx_status s = prepare(c);
+  if (s != FRBX_OK) return s;
+  const int N = c->N, J = c->J;
+  double fr = 0.0;
+  for (int n = 0; n < N; ++n) fr = std::max(fr, c->f0[n] + (J - 1) * c->df);
+  double sx = 0.0;
+  for (int n = 0; n < N; ++n)
+    for (int j = 1; j < J; ++j) {
+      const double f = c->f0[n] + j * c->df;
+      sx += c->k_dm * (1.0 / (f * f) - 1.0 / (fr * fr)) / c->t_ap;
+    }
+  c->rxbar = J > 1 ? sx / double(N * (J - 1)) : 0.0;
+  c->rcells[0] = 1.0 / (double(c->sbd_pad) * J * c->df);
+  c->rcells[1] = c->mbd_step;
+  c->rcells[2] = c->n_rate > 1 ? c->rate_step : 0.0;
+  c->rcells[3] = c->dm_step;
+  c->rcells[4] = 1.0;
+  for (int k = 0; k < 5; ++k)
+    if (cells) cells[k] = c->rcells[k];
+  if (xbar) *xbar = c->rxbar;
+  return FRBX_OK;
+}
+
+frbx_status frbx_refine_begin(frbx_ctx *c, const frbx_candidate *peaks, int64_t n, double *theta0) {
+  if (!c || n < 0 || (n > 0 && !peaks)) return FRBX_E_INVAL;
+  if (!c->loaded || c->streaming) return c->fail(FRBX_E_STATE, "refinement needs input loaded with frbx_load");
+  if (n > (int64_t(1) << 31) - 1) return c->fail(FRBX_E_RANGE, "too many peaks");
+  if (hipSetDevice(c->device) != hipSuccess) return c->fail(FRBX_E_DEVICE, "hipSetDevice failed");
+  frbx_status s = frbx_refine_cells(c, nullptr, nullptr);
+  if (s != FRBX_OK) return s;
+  const int N = c->N, J = c->J, NJ = N * J, PJ = c->sbd_pad * J, M = c->n_mbd;
+  std::vector<frbx::RefineSeg> seg(static_cast<size_t>(n));
+  std::vector<double> th(static_cast<size_t>(n) * 5);
+  for (int64_t i = 0; i < n; ++i) {
+    const frbx_candidate &p = peaks[i];
+    if (p.baseline < 0 || p.baseline >= c->B || p.dm_index < 0 || p.dm_index >= c->n_dm || p.window_len < 1 ||
+        p.window_len > c->K || p.k0 < 0 || p.k0 >= c->K || p.rate_idx < 0 || p.rate_idx >= c->n_rate ||
+        p.sbd_idx < 0 || p.sbd_idx >= PJ || p.mbd_idx < 0 || p.mbd_idx >= M)
+      return c->fail(FRBX_E_INVAL, "peak record out of range");
+    seg[i] = frbx::RefineSeg{p.baseline, p.window_len, p.k0};
+    th[5 * i + 0] = (p.sbd_idx - PJ / 2.0) / (PJ * c->df);
+    th[5 * i + 1] = (p.mbd_idx - M / 2.0) * c->mbd_step;
+    th[5 * i + 2] = (p.rate_idx - c->n_rate / 2) * c->rate_step;
+    th[5 * i + 3] = c->dm_lo + p.dm_index * c->dm_step;
+    th[5 * i + 4] = 0.0;
+  }
+  double fr = 0.0;
+  for (int nn = 0; nn < N; ++nn) fr = std::max(fr, c->f0[nn] + (J - 1) * c->df);
+  std::vector<frbx::RefineChan> ch(NJ);
+  for (int nn = 0; nn < N; ++nn)
+    for (int j = 0; j < J; ++j) {
+      const double f = c->f0[nn] + j * c->df;
+      ch[nn * J + j] = frbx::RefineChan{j * c->df, c->f0[nn] - c->f0[0], 1e3 * c->f0[nn] * c->t_ap,
+                                        c->k_dm * (1.0 / (f * f) - 1.0 / (fr * fr)) / c->t_ap};
+    }
+  const size_t nn_alloc = size_t(std::max<int64_t>(n, 1));
+  if ((s = ensure(c, c->d_rseg, c->rseg_cap, nn_alloc)) != FRBX_OK) return s;
+  if ((s = ensure(c, c->d_rtheta, c->rtheta_cap, nn_alloc * 5)) != FRBX_OK) return s;
+  if ((s = ensure(c, c->d_rpower, c->rpower_cap, nn_alloc)) != FRBX_OK) return s;
+  if ((s = ensure(c, c->d_rchan, c->rchan_cap, size_t(NJ))) != FRBX_OK) return s;
+  if (n > 0) {
+    if ((s = c->hip(hipMemcpyAsync(c->d_rseg, seg.data(), seg.size() * sizeof(frbx::RefineSeg),
+                                   hipMemcpyHostToDevice, c->stream), "refine upload")) != FRBX_OK)
+      return s;
+    if ((s = c->hip(hipMemcpyAsync(c->d_rtheta, th.data(), th.size() * sizeof(double), hipMemcpyHostToDevice,
+                                   c->stream), "refine upload")) != FRBX_OK)
+      return s;
+  }
+  if ((s = c->hip(hipMemcpyAsync(c->d_rchan, ch.data(), ch.size() * sizeof(frbx::RefineChan),
+                                 hipMemcpyHostToDevice, c->stream), "refine upload")) != FRBX_OK)
+    return s;
+  if ((s = c->hip(hipStreamSynchronize(c->stream), "refine upload")) != FRBX_OK) return s;
+  c->rn = n;
+  c->rdone = false;
+  c->rbegun = true;
+  if (theta0) std::copy(th.begin(), th.end(), theta0);
+  return FRBX_OK;
+}
+
+frbx_status frbx_refine_run(frbx_ctx *c, int32_t n_steps) {
+  frbx_status s = refine_ready(c);
+  if (s != FRBX_OK) return s;
+  if (n_steps < 0) return c->fail(FRBX_E_INVAL, "n_steps < 0");
+  c->spans.clear();
+  c->ev_used = 0;
+  frbx::RefineArgs a = refine_args(c);
+  a.theta = c->d_rtheta;
+  a.power = c->d_rpower;
+  for (int k = 0; k <= n_steps; ++k) {
+    const int mode = k < n_steps ? frbx::kRefineStep : frbx::kRefineForward;
+    const int sp = c->span_begin(3, c->rn);
+    if ((s = c->hip(frbx::launch_refine(mode, a, c->stream), "refine launch")) != FRBX_OK) return s;
+    c->span_end(sp);
+  }
+  if ((s = c->hip(hipStreamSynchronize(c->stream), "refine")) != FRBX_OK) return s;
+  if (c->timing) c->collect_timing();
+  c->rdone = true;
+  return FRBX_OK;
+}
+
+frbx_status frbx_refine_results(const frbx_ctx *cc, double *theta, float *power, int64_t cap, int64_t *n) {
+  frbx_ctx *c = const_cast<frbx_ctx *>(cc);
+  if (!c || !n) return FRBX_E_INVAL;
+  if (!c->rdone) return FRBX_E_STATE;
+  *n = c->rn;
+  if (cap < c->rn) return FRBX_E_RANGE;
+  if (hipSetDevice(c->device) != hipSuccess) return c->fail(FRBX_E_DEVICE, "hipSetDevice failed");
+  frbx_status s;
+  if (theta && c->rn > 0 &&
+      (s = c->hip(hipMemcpy(theta, c->d_rtheta, size_t(c->rn) * 5 * sizeof(double), hipMemcpyDeviceToHost),
+                  "refine results")) != FRBX_OK)
+    return s;
+  if (power && c->rn > 0 &&
+      (s = c->hip(hipMemcpy(power, c->d_rpower, size_t(c->rn) * sizeof(float), hipMemcpyDeviceToHost),
+                  "refine results")) != FRBX_OK)
+    return s;
+  return FRBX_OK;
+}
+
+frbx_status frbx_refine_forward(frbx_ctx *c, const double *theta, float *power) {
+  frbx_status s = refine_ready(c);
+  if (s != FRBX_OK) return s;
+  if (!theta || !power) return c->fail(FRBX_E_INVAL, "null device pointer");
+  frbx::RefineArgs a = refine_args(c);
+  a.theta = const_cast<double *>(theta);
+  a.power = power;
+  return c->hip(frbx::launch_refine(frbx::kRefineForward, a, c->stream), "refine forward");
+}
+
+frbx_status frbx_refine_backward(frbx_ctx *c, const double *theta, const float *grad_power, double *grad_theta) {
+  frbx_status s = refine_ready(c);
+  if (s != FRBX_OK) return s;
+  if (!theta || !grad_power || !grad_theta) return c->fail(FRBX_E_INVAL, "null device pointer");
+  frbx::RefineArgs a = refine_args(c);
+  a.theta = const_cast<double *>(theta);
+  a.grad_power = grad_power;
+  a.grad_theta = grad_theta;
+  return c->hip(frbx::launch_refine(frbx::kRefineBackward, a, c->stream), "refine backward");
+}
+
+frbx_status frbx_refine_curvature(frbx_ctx *c, const double *theta, double *curv) {
+  frbx_status s = refine_ready(c);
+  if (s != FRBX_OK) return s;
+  if (!theta || !curv) return c->fail(FRBX_E_INVAL, "null device pointer");
+  frbx::RefineArgs a = refine_args(c);
+  a.theta = const_cast<double *>(theta);
+  a.curv = curv;
+  return c->hip(frbx::launch_refine(frbx::kRefineCurvature, a, c->stream), "refine curvature");
 }
 
 frbx_status frbx_set_timing(frbx_ctx *c, int enable) {

@@ -133,6 +133,42 @@ hipError_t launch_ingest(const void *src, int src_kind, const float *scale, int6
 hipError_t launch_carry(const float2 *src, float2 *dst, int n_ch, int64_t frames, int64_t from, int64_t n,
                         hipStream_t s);
 
+// Refinement of coarse peaks: |G| of one segment at continuous (SBD, MBD,
+// rate, DM, arrival offset), Eq. 5 with the rate term of Eq. 4 and the frames
+// of Eq. 3 taken at the unrounded Eq. 1 shift (Keys cubic interpolation).
+struct RefineChan {   // per channel c = n * J + j
+  double fj;          // j * chan_bw (MHz)
+  double fm;          // f0^n - f0^0 (MHz)
+  double wr;          // 1e3 f0^n t_ap: rate phase in cycles per unit rate and AP
+  double dxd;         // k_DM (f^-2 - f_ref^-2) / t_ap: APs of shift per unit DM
+};
+struct RefineSeg {
+  int32_t b;          // baseline
+  int32_t l;          // window length (APs)
+  int64_t k0;         // first AP of the segment at f_ref
+};
+enum RefineMode { kRefineForward = 0, kRefineBackward = 1, kRefineCurvature = 2, kRefineStep = 3 };
+struct RefineArgs {
+  const void *vis;           // [B][NJ][row_stride] complex64, or complex32 when in_f16
+  int32_t in_f16;
+  int64_t n_frames;          // APs per channel
+  int64_t row_stride;
+  int32_t nj, J;
+  const RefineChan *chan;    // [NJ]
+  const float2 *cal;         // [B][NJ]
+  const RefineSeg *seg;      // [n]
+  int32_t n;
+  double *theta;             // [n][5] (sbd us, mbd us, rate, DM, t APs); updated by a step
+  float *power;              // [n] |G| (forward; step: before the step)
+  const float *grad_power;   // [n] backward: upstream gradient
+  double *grad_theta;        // [n][5] backward: grad_power * dP/dtheta
+  double *curv;              // [n][6] curvature: d2P/dtheta_i^2 (5), d2P/dDM dt
+  double cells[5];           // step: grid cell of each parameter (0: held)
+  double dm_t;               // step: arrival-offset cells moved per DM cell (-xbar c_DM / c_t)
+  double max_step;           // step: largest move per coordinate, cells
+};
+hipError_t launch_refine(int mode, const RefineArgs &a, hipStream_t s);
+
 // max(|re|, |im|) over n complex values (float32 or float16 pairs) into
 // *out (float bits, caller zeroes it first)
 hipError_t launch_absmax(const void *vis, int64_t n, int in_f16, unsigned int *out,

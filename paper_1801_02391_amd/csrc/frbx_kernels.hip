@@ -848,6 +848,207 @@ __global__ __launch_bounds__(kBlock) void absmax_kernel(const void *vis, int64_t
   if ((threadIdx.x & 63) == 0) atomicMax(out, __float_as_uint(m));
 }
 
+// ------------------------------------------------------- refinement kernel
+// exp(-2 pi i x) for x in cycles, reduced in float64 before the float sincos
+__device__ __forceinline__ float2 cis_neg(double x) {
+  const float f = float(x - rint(x));
+  float sn, cs;
+  sincospif(2.0f * f, &sn, &cs);
+  return make_float2(cs, -sn);
+}
+
+// Keys cubic (a = -1/2) weights of the samples at -1, 0, 1, 2 for a point at
+// fraction al of the way from sample 0 to sample 1, and (D >= 1) their first
+// and (D >= 2) second derivatives with respect to the position.
+template <int D>
+__device__ __forceinline__ void keys_weights(float al, float (&w)[4], float (&w1)[4], float (&w2)[4]) {
+  const float a2 = al * al, a3 = a2 * al;
+  w[0] = 0.5f * (-a3 + 2.f * a2 - al);
+  w[1] = 0.5f * (3.f * a3 - 5.f * a2 + 2.f);
+  w[2] = 0.5f * (-3.f * a3 + 4.f * a2 + al);
+  w[3] = 0.5f * (a3 - a2);
+  if constexpr (D >= 1) {
+    w1[0] = 0.5f * (-3.f * a2 + 4.f * al - 1.f);
+    w1[1] = 0.5f * (9.f * a2 - 10.f * al);
+    w1[2] = 0.5f * (-9.f * a2 + 8.f * al + 1.f);
+    w1[3] = 0.5f * (3.f * a2 - 2.f * al);
+  }
+  if constexpr (D >= 2) {
+    w2[0] = -3.f * al + 2.f;
+    w2[1] = 9.f * al - 5.f;
+    w2[2] = -9.f * al + 4.f;
+    w2[3] = 3.f * al - 1.f;
+  }
+}
+
+__device__ __forceinline__ float2 cscale(float2 a, float s) { return make_float2(a.x * s, a.y * s); }
+__device__ __forceinline__ float2 cfma(float2 acc, float2 a, float w) {
+  return make_float2(fmaf(a.x, w, acc.x), fmaf(a.y, w, acc.y));
+}
+
+// One work-group per peak.  Every thread walks channels c = tid + 256 i,
+// forms the rate-rotated window sum of the interpolated frames (and the
+// derivative sums the mode needs), rotates by the delay phase and the
+// calibration, and accumulates; a block reduction gives G and its
+// derivatives, from which thread 0 writes the mode's output.
+template <int MODE>
+__global__ __launch_bounds__(kBlock) void refine_kernel(RefineArgs a) {
+  constexpr int D = MODE == kRefineForward ? 0 : MODE == kRefineBackward ? 1 : 2;
+  constexpr int NA = D == 0 ? 1 : D == 1 ? 6 : 12;
+  const int p = blockIdx.x;
+  const RefineSeg sg = a.seg[p];
+  const double ts = a.theta[5 * p + 0], tm = a.theta[5 * p + 1], rho = a.theta[5 * p + 2];
+  const double dm = a.theta[5 * p + 3], toff = a.theta[5 * p + 4];
+  const int l = sg.l;
+  const float uc = 0.5f * float(l - 1);
+  const size_t esz = a.in_f16 ? 4 : 8;
+  const void *vb = static_cast<const char *>(a.vis) + size_t(sg.b) * size_t(a.nj) * size_t(a.row_stride) * esz;
+  const float2 *calb = a.cal + size_t(sg.b) * a.nj;
+  float2 acc[NA];
+  for (int i = 0; i < NA; ++i) acc[i] = make_float2(0.f, 0.f);
+
+  for (int c = threadIdx.x; c < a.nj; c += kBlock) {
+    if (c % a.J == 0) continue;  // the DC point is not fitted
+    const RefineChan ch = a.chan[c];
+    double pos = double(sg.k0) + toff + ch.dxd * dm;
+    pos = fmin(fmax(pos, -8.0), double(a.n_frames) + 8.0);  // also maps NaN into range
+    const double fl = floor(pos);
+    const int64_t i0 = int64_t(fl) - 1;
+    float w[4], w1[4], w2[4];
+    keys_weights<D>(float(pos - fl), w, w1, w2);
+    float2 S0 = make_float2(0.f, 0.f), S1 = S0, S11 = S0, S2 = S0, S3 = S0;
+    const int64_t rowoff = int64_t(c) * a.row_stride;
+    for (int u = 0; u < l; ++u) {
+      const float du = float(u) - uc;
+      const float2 r = cis_neg(rho * ch.wr * double(du));
+      float2 val = make_float2(0.f, 0.f), d1 = val, d2 = val;
+#pragma unroll
+      for (int m = 0; m < 4; ++m) {
+        const int64_t k = i0 + u + m;
+        const float2 v = (k >= 0 && k < a.n_frames) ? load_vis(vb, rowoff + k, a.in_f16 != 0) : make_float2(0.f, 0.f);
+        val = cfma(val, v, w[m]);
+        if constexpr (D >= 1) d1 = cfma(d1, v, w1[m]);
+        if constexpr (D >= 2) d2 = cfma(d2, v, w2[m]);
+      }
+      const float2 rv = cmul(r, val);
+      S0 = cadd(S0, rv);
+      if constexpr (D >= 1) {
+        S1 = cfma(S1, rv, du);
+        S2 = cadd(S2, cmul(r, d1));
+      }
+      if constexpr (D >= 2) {
+        S11 = cfma(S11, rv, du * du);
+        S3 = cadd(S3, cmul(r, d2));
+      }
+    }
+    const float2 e = cmul(calb[c], cis_neg(ch.fj * ts + ch.fm * tm));
+    const float2 term = cmul(e, S0);
+    acc[0] = cadd(acc[0], term);
+    if constexpr (D >= 1) {
+      const float fj = float(ch.fj), fm = float(ch.fm), wr = float(ch.wr), dx = float(ch.dxd);
+      const float2 eS2 = cmul(e, S2);
+      acc[1] = cfma(acc[1], term, fj);
+      acc[2] = cfma(acc[2], term, fm);
+      acc[3] = cfma(acc[3], cmul(e, S1), wr);
+      acc[4] = cfma(acc[4], eS2, dx);
+      acc[5] = cadd(acc[5], eS2);
+      if constexpr (D >= 2) {
+        const float2 eS3 = cmul(e, S3);
+        acc[6] = cfma(acc[6], term, fj * fj);
+        acc[7] = cfma(acc[7], term, fm * fm);
+        acc[8] = cfma(acc[8], cmul(e, S11), wr * wr);
+        acc[9] = cfma(acc[9], eS3, dx * dx);
+        acc[10] = cadd(acc[10], eS3);
+        acc[11] = cfma(acc[11], eS3, dx);
+      }
+    }
+  }
+
+  // block reduction: wave shuffles, then one LDS row per wave
+  __shared__ float2 red[kBlock / 64][NA];
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+#pragma unroll
+  for (int i = 0; i < NA; ++i) {
+    float2 v = acc[i];
+    for (int off = 32; off > 0; off >>= 1) {
+      v.x += __shfl_xor(v.x, off, 64);
+      v.y += __shfl_xor(v.y, off, 64);
+    }
+    if (lane == 0) red[wv][i] = v;
+  }
+  __syncthreads();
+  if (threadIdx.x != 0) return;
+  double gr[NA], gi[NA];
+  for (int i = 0; i < NA; ++i) {
+    gr[i] = 0.0;
+    gi[i] = 0.0;
+    for (int k = 0; k < kBlock / 64; ++k) {
+      gr[i] += double(red[k][i].x);
+      gi[i] += double(red[k][i].y);
+    }
+  }
+  const double P = sqrt(gr[0] * gr[0] + gi[0] * gi[0]);
+  if constexpr (MODE == kRefineForward) {
+    a.power[p] = float(P);
+  } else {
+    const double tp = 2.0 * M_PI, tp2 = tp * tp;
+    // first derivatives: dG/dtau_s = -2 pi i sum f_j term, likewise MBD and rate
+    double dr[5], di[5];
+    for (int k = 0; k < 3; ++k) {
+      dr[k] = tp * gi[1 + k];
+      di[k] = -tp * gr[1 + k];
+    }
+    dr[3] = gr[4]; di[3] = gi[4];
+    dr[4] = gr[5]; di[4] = gi[5];
+    double g[5];
+    for (int k = 0; k < 5; ++k) g[k] = P > 0.0 ? (gr[0] * dr[k] + gi[0] * di[k]) / P : 0.0;
+    if constexpr (MODE == kRefineBackward) {
+      const double up = double(a.grad_power[p]);
+      for (int k = 0; k < 5; ++k) a.grad_theta[5 * p + k] = up * g[k];
+    } else {
+      double h[6] = {0, 0, 0, 0, 0, 0};
+      if (P > 0.0) {
+        double sr[6], si[6];
+        for (int k = 0; k < 3; ++k) {  // (-2 pi i)^2 = -4 pi^2
+          sr[k] = -tp2 * gr[6 + k];
+          si[k] = -tp2 * gi[6 + k];
+        }
+        for (int k = 3; k < 6; ++k) {
+          sr[k] = gr[6 + k];
+          si[k] = gi[6 + k];
+        }
+        for (int k = 0; k < 5; ++k)
+          h[k] = (dr[k] * dr[k] + di[k] * di[k] + gr[0] * sr[k] + gi[0] * si[k]) / P - g[k] * g[k] / P;
+        h[5] = (dr[3] * dr[4] + di[3] * di[4] + gr[0] * sr[5] + gi[0] * si[5]) / P - g[3] * g[4] / P;
+      }
+      if constexpr (MODE == kRefineCurvature) {
+        for (int k = 0; k < 6; ++k) a.curv[6 * p + k] = h[k];
+      } else {
+        // Newton step in grid cells; the DM coordinate carries the arrival
+        // offset along (dm_t offset cells per DM cell)
+        const double *c = a.cells;
+        const double at = a.dm_t;
+        double gz[5], hz[5];
+        for (int k = 0; k < 5; ++k) {
+          gz[k] = g[k] * c[k];
+          hz[k] = h[k] * c[k] * c[k];
+        }
+        gz[3] += at * g[4] * c[4];
+        hz[3] += 2.0 * at * h[5] * c[3] * c[4] + at * at * h[4] * c[4] * c[4];
+        double st[5];
+        for (int k = 0; k < 5; ++k) {
+          double s = hz[k] < 0.0 ? -gz[k] / hz[k] : a.max_step * double((gz[k] > 0.0) - (gz[k] < 0.0));
+          s = fmin(fmax(s, -a.max_step), a.max_step);
+          st[k] = c[k] > 0.0 ? s : 0.0;
+        }
+        st[4] += at * st[3];
+        for (int k = 0; k < 5; ++k) a.theta[5 * p + k] += c[k] * st[k];
+        a.power[p] = float(P);
+      }
+    }
+  }
+}
+
 }  // namespace
 
 // ---------------------------------------------------------------- launchers
@@ -1072,6 +1273,19 @@ hipError_t launch_absmax(const void *vis, int64_t n, int in_f16, unsigned int *o
   const int64_t blocks = std::min<int64_t>(4096, (n + kBlock - 1) / kBlock);
   if (blocks <= 0) return hipSuccess;
   hipLaunchKernelGGL(absmax_kernel, dim3(unsigned(blocks)), dim3(kBlock), 0, s, vis, n, in_f16, out);
+  return hipGetLastError();
+}
+
+hipError_t launch_refine(int mode, const RefineArgs &a, hipStream_t s) {
+  (void)hipGetLastError();
+  if (a.n <= 0) return hipSuccess;
+  switch (mode) {
+    case kRefineForward: hipLaunchKernelGGL(refine_kernel<kRefineForward>, dim3(a.n), dim3(kBlock), 0, s, a); break;
+    case kRefineBackward: hipLaunchKernelGGL(refine_kernel<kRefineBackward>, dim3(a.n), dim3(kBlock), 0, s, a); break;
+    case kRefineCurvature: hipLaunchKernelGGL(refine_kernel<kRefineCurvature>, dim3(a.n), dim3(kBlock), 0, s, a); break;
+    case kRefineStep: hipLaunchKernelGGL(refine_kernel<kRefineStep>, dim3(a.n), dim3(kBlock), 0, s, a); break;
+    default: return hipErrorInvalidValue;
+  }
   return hipGetLastError();
 }
 

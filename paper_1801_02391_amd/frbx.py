@@ -51,7 +51,8 @@ class Timing(C.Structure):
     _fields_ = [("fringe_ms", C.c_double), ("n_fringe", C.c_int64), ("fringe_units", C.c_int64),
                 ("dedisperse_ms", C.c_double), ("n_dedisperse", C.c_int64),
                 ("dedisperse_units", C.c_int64), ("stats_ms", C.c_double), ("n_stats", C.c_int64),
-                ("dedisperse_bytes", C.c_int64)]
+                ("dedisperse_bytes", C.c_int64), ("refine_ms", C.c_double), ("n_refine", C.c_int64),
+                ("refine_units", C.c_int64)]
 
 
 CANDIDATE_FIELDS = [f for f, _ in Candidate._fields_ if f != "reserved"]
@@ -85,6 +86,14 @@ _SIGS = {
     "frbx_stream_begin": ([_P, C.c_int64], C.c_int),
     "frbx_stream_push": ([_P, _P, C.c_int32, _P, C.c_int], C.c_int),
     "frbx_stream_position": ([_P, _P, _P, _P], C.c_int),
+    "frbx_top_peaks": ([_P, C.c_int64, _P, C.c_int64, C.POINTER(C.c_int64)], C.c_int),
+    "frbx_refine_cells": ([_P, _P, _P], C.c_int),
+    "frbx_refine_begin": ([_P, _P, C.c_int64, _P], C.c_int),
+    "frbx_refine_run": ([_P, C.c_int32], C.c_int),
+    "frbx_refine_results": ([_P, _P, _P, C.c_int64, C.POINTER(C.c_int64)], C.c_int),
+    "frbx_refine_forward": ([_P, _P, _P], C.c_int),
+    "frbx_refine_backward": ([_P, _P, _P, _P], C.c_int),
+    "frbx_refine_curvature": ([_P, _P, _P], C.c_int),
     "frbx_power_sum": ([_P, _P, C.c_int32, _P, C.c_int64, _P], C.c_int),
     "frbx_calibrate": ([_P, C.c_int32, C.c_int64, C.c_int32, _P, _P], C.c_int),
     "frbx_get_timing": ([_P, _P], C.c_int),
@@ -135,6 +144,18 @@ def records_to_dicts(arr):
     return [{f: (getattr(r, f)) for f in CANDIDATE_FIELDS} for r in arr]
 
 
+def dicts_to_records(items):
+    """Candidate dicts (fields as returned by the getters) -> a ctypes array."""
+    arr = (Candidate * max(1, len(items)))()
+    for i, c in enumerate(items):
+        for f in CANDIDATE_FIELDS:
+            if f in c:
+                setattr(arr[i], f, c[f])
+        if "group_id" not in c:
+            arr[i].group_id = -1
+    return arr
+
+
 def ap_offsets(layout, dm_lo, dm_step, n_dm, k_dm=0.0):
     """Host-only Eq. 2 table [D][N][J] from the library (no device needed)."""
     st, f0 = _layout_struct(layout)
@@ -149,13 +170,7 @@ def detect(crossings, t_amb_us, n_win_min, n_bl_min, use_mbd=True):
     """Host-only grouping (steps b-d, best DM, cross matching) over a list of
     crossing dicts with at least baseline, dm_index, window_len, k0,
     power_norm, mbd_us.  Returns (detections, groups) as lists of dicts."""
-    arr = (Candidate * max(1, len(crossings)))()
-    for i, c in enumerate(crossings):
-        for f in CANDIDATE_FIELDS:
-            if f in c:
-                setattr(arr[i], f, c[f])
-        if "group_id" not in c:
-            arr[i].group_id = -1
+    arr = dicts_to_records(crossings)
     nd, ng = C.c_int64(0), C.c_int64(0)
     L = lib()
     s = L.frbx_detect(arr, len(crossings), t_amb_us, n_win_min, n_bl_min, int(bool(use_mbd)),
@@ -388,6 +403,113 @@ class Search:
                   "calibrate")
         return t, p
 
+    # ----------------------------------------------------------- refinement
+    REFINE_PARAMS = ("sbd_us", "mbd_us", "rate", "dm", "t_frames")
+
+    def top_peaks(self, n_max):
+        """The n_max crossings of the last run with the highest normalised power."""
+        L = lib()
+        n = C.c_int64(0)
+        s = L.frbx_top_peaks(self._h, int(n_max), None, 0, C.byref(n))
+        if s not in (OK, E_RANGE):
+            self._chk(s, "top_peaks")
+        arr = (Candidate * max(1, n.value))()
+        self._chk(L.frbx_top_peaks(self._h, int(n_max), arr, n.value, C.byref(n)), "top_peaks")
+        return records_to_dicts(arr[:n.value])
+
+    def refine_cells(self):
+        cells = np.zeros(5)
+        xbar = C.c_double(0.0)
+        self._chk(lib().frbx_refine_cells(self._h, _ptr(cells), C.byref(xbar)), "refine_cells")
+        return cells, xbar.value
+
+    def refine_begin(self, peaks):
+        """Start a refinement of the given candidate records (dicts or
+        Candidate records); returns the start parameters [n][5]."""
+        recs = dicts_to_records(peaks)
+        n = len(peaks)
+        th0 = np.zeros((max(n, 1), 5))
+        self._chk(lib().frbx_refine_begin(self._h, recs, n, _ptr(th0)), "refine_begin")
+        self._refine_n = n
+        return th0[:n]
+
+    def refine(self, peaks, steps=20):
+        """The library's ascent: (start theta [n][5], final theta [n][5], final |G| [n])."""
+        th0 = self.refine_begin(peaks)
+        self._chk(lib().frbx_refine_run(self._h, int(steps)), "refine_run")
+        n = C.c_int64(0)
+        th = np.zeros((max(len(peaks), 1), 5))
+        p = np.zeros(max(len(peaks), 1), dtype=np.float32)
+        self._chk(lib().frbx_refine_results(self._h, _ptr(th), _ptr(p), len(peaks), C.byref(n)),
+                  "refine_results")
+        return th0, th[:n.value], p[:n.value]
+
+    def _dev(self, t, dtype, shape):
+        torch = self._torch
+        if (not isinstance(t, torch.Tensor) or t.dtype != dtype or t.device.type != "cuda"
+                or not t.is_contiguous() or tuple(t.shape) != tuple(shape)):
+            raise FrbxError(E_INVAL, f"expected a contiguous {dtype} GPU tensor of shape {shape}")
+        return _P(t.data_ptr())
+
+    def refine_forward(self, theta):
+        """|G| at theta [n][5] (float64 GPU tensor) of the begun peaks."""
+        torch = self._torch
+        n = self._refine_n
+        out = torch.empty(n, dtype=torch.float32, device=theta.device)
+        self._chk(lib().frbx_refine_forward(self._h, self._dev(theta, torch.float64, (n, 5)),
+                                            self._dev(out, torch.float32, (n,))), "refine_forward")
+        return out
+
+    def refine_backward(self, theta, grad_power):
+        torch = self._torch
+        n = self._refine_n
+        g = torch.empty((n, 5), dtype=torch.float64, device=theta.device)
+        self._chk(lib().frbx_refine_backward(self._h, self._dev(theta, torch.float64, (n, 5)),
+                                             self._dev(grad_power, torch.float32, (n,)),
+                                             self._dev(g, torch.float64, (n, 5))), "refine_backward")
+        return g
+
+    def refine_curvature(self, theta):
+        torch = self._torch
+        n = self._refine_n
+        h = torch.empty((n, 6), dtype=torch.float64, device=theta.device)
+        self._chk(lib().frbx_refine_curvature(self._h, self._dev(theta, torch.float64, (n, 5)),
+                                              self._dev(h, torch.float64, (n, 6))), "refine_curvature")
+        return h
+
+    def refine_autograd(self, peaks, steps=20, max_step=0.5):
+        """The same ascent driven through the torch.autograd.Function: each
+        step evaluates P (forward kernel), back-propagates P.sum() (backward
+        kernel), takes the curvature (curvature kernel) and moves theta by the
+        Newton step of the library's ascent.  Returns (theta0, theta, P)."""
+        torch = self._torch
+        th0 = self.refine_begin(peaks)
+        cells_np, xbar = self.refine_cells()
+        dev = f"cuda:{self.device}"
+        cells = torch.tensor(cells_np, dtype=torch.float64, device=dev)
+        a = -xbar * cells_np[3] / cells_np[4] if cells_np[4] > 0 else 0.0
+        live = cells > 0
+        theta = torch.tensor(th0, dtype=torch.float64, device=dev).requires_grad_(True)
+        for _ in range(steps):
+            P = refine_power(theta, self)
+            P.sum().backward()
+            with torch.no_grad():
+                g = theta.grad
+                H = self.refine_curvature(theta.detach().contiguous())
+                gz = g * cells
+                gz[:, 3] += a * g[:, 4] * cells[4]
+                hz = H[:, :5] * cells * cells
+                hz[:, 3] += 2 * a * H[:, 5] * cells[3] * cells[4] + a * a * H[:, 4] * cells[4] ** 2
+                newton = -gz / torch.where(hz < 0, hz, -torch.ones_like(hz))
+                st = torch.where(hz < 0, newton, max_step * torch.sign(gz)).clamp(-max_step, max_step)
+                st = torch.where(live, st, torch.zeros_like(st))
+                st[:, 4] += a * st[:, 3]
+                theta += cells * st
+            theta.grad = None
+        with torch.no_grad():
+            P = self.refine_forward(theta.detach().contiguous())
+        return th0, theta.detach().cpu().numpy(), P.cpu().numpy()
+
     def set_timing(self, enable=True):
         self._chk(lib().frbx_set_timing(self._h, int(bool(enable))), "set_timing")
 
@@ -406,3 +528,38 @@ class Search:
         self._chk(lib().frbx_dump_segment(self._h, b, d, wi, q, _P(out.data_ptr())),
                   "dump_segment")
         return out.cpu().numpy().reshape(R, PJ, M)
+
+
+def _refine_function():
+    import torch
+
+    class RefinePower(torch.autograd.Function):
+        """P = |G|(theta) of the begun peaks: forward and backward are the
+        library's refinement kernels (float32 sums, float64 phases)."""
+
+        @staticmethod
+        def forward(ctx, theta, search):
+            th = theta.detach().contiguous()
+            ctx.save_for_backward(th)
+            ctx.search = search
+            return search.refine_forward(th)
+
+        @staticmethod
+        def backward(ctx, grad_power):
+            (th,) = ctx.saved_tensors
+            g = ctx.search.refine_backward(th, grad_power.detach().to(torch.float32).contiguous())
+            return g, None
+
+    return RefinePower
+
+
+_REFINE_FN = None
+
+
+def refine_power(theta, search):
+    """torch.autograd entry: |G| [n] of the peaks begun on `search` at
+    theta [n][5] (float64 GPU tensor, requires_grad allowed)."""
+    global _REFINE_FN
+    if _REFINE_FN is None:
+        _REFINE_FN = _refine_function()
+    return _REFINE_FN.apply(theta, search)
