@@ -59,14 +59,15 @@ def cpu_baseline(wl, V, target_s=15.0):
                                np.zeros(lay["n_if"]))
     d = srch["n_dm"] // 2
     PJ, M, R = len(g["tau_s"]), len(g["tau_m"]), len(g["rates"])
-    t0 = time.perf_counter()
     O.search_row(V[0], g, cal, d, 0, q_list=[0], chunk=1)       # warm caches / BLAS
-    one = time.perf_counter() - t0
-    n = max(1, int(target_s / max(one, 1e-3)))
-    n = min(n, g["segs"][0][2])
+    Q = g["segs"][0][2]
+    n, el = 0, 0.0
     t0 = time.perf_counter()
-    O.search_row(V[0], g, cal, d, 0, q_list=list(range(n)), chunk=8)
-    el = time.perf_counter() - t0
+    while el < target_s and n < Q:
+        k = min(8, Q - n)
+        O.search_row(V[0], g, cal, d, 0, q_list=list(range(n, n + k)), chunk=8)
+        n += k
+        el = time.perf_counter() - t0
     cells = n * R * PJ * M
     return {"value": cells / el, "unit": "cells/s", "cores": int(threads), "kind": "oracle",
             "sample": f"{n} segments (window {g['segs'][0][0]} APs, baseline 0, DM trial {d}) "
@@ -74,7 +75,94 @@ def cpu_baseline(wl, V, target_s=15.0):
                       f"{el:.1f} s"}
 
 
-def run_form(args, wl, V, prec, dev):
+def refine_leg(args, wl, s, truth):
+    """Refinement of the top coarse peaks (by normalised power) after the
+    search: the library's ascent timed with HIP events, the gradient of the
+    backward kernel against central differences of the device forward, and
+    the distance of the refined parameters from the injected truth for the
+    peaks that belong to an injected pulse."""
+    import numpy as np
+    import torch
+    lay, srch = wl["layout"], wl["search"]
+    peaks = s.top_peaks(args.refine_peaks)
+    n = len(peaks)
+    if n == 0:
+        return {"peaks": 0}
+    s.refine(peaks, steps=args.refine_steps)       # warm-up (allocations, code load)
+    s.set_timing(True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    th0, th, P = s.refine(peaks, steps=args.refine_steps)
+    el = time.perf_counter() - t0
+    tim = s.timing()
+    cells, _ = s.refine_cells()
+    # gradient check on the device: central differences of the float32
+    # forward; steps of 1e-3 cell for the delays and rate, and steps that
+    # move the lowest channel by 0.01 AP for DM and the arrival offset (a DM
+    # cell can shift it by many APs); error relative to max(|fd|, 0.1 P/cell)
+    f0 = np.asarray(lay["if_freq_mhz"], dtype=np.float64)
+    f_lo, f_hi = f0.min(), f0.max() + (lay["n_chan"] - 1) * lay["chan_bw_mhz"]
+    kdm = srch.get("k_dm", 4.149e6) or 4.149e6
+    dx_max = kdm * (1.0 / f_lo ** 2 - 1.0 / f_hi ** 2) / lay["t_ap_ms"]
+    steps_h = [1e-3 * cells[0], 1e-3 * cells[1], 1e-3 * cells[2], 1e-2 / max(dx_max, 1e-12), 1e-2]
+    tt = torch.tensor(th0 + 0.25 * np.where(cells > 0, cells, 0.0), dtype=torch.float64, device="cuda")
+    g = s.refine_backward(tt, torch.ones(n, dtype=torch.float32, device="cuda")).cpu().numpy()
+    Pt = s.refine_forward(tt).cpu().numpy()
+    fd_err = []
+    for k in range(5):
+        if cells[k] == 0:
+            continue
+        e = torch.zeros_like(tt)
+        e[:, k] = steps_h[k]
+        fd = ((s.refine_forward(tt + e).double() - s.refine_forward(tt - e).double()) / (2 * steps_h[k])).cpu().numpy()
+        fd_err.append(np.abs(g[:, k] - fd) / np.maximum(np.abs(fd), 1e-1 * Pt / cells[k]))
+    fd_err = np.concatenate(fd_err)
+    # truth: pulse-associated peaks (baseline, time overlap at f_ref, DM within 2 cells)
+    t_ap = lay["t_ap_ms"]
+    t_amb = cells[1] * srch["n_mbd"]
+    errs, dm_errs = [], []
+    for i, p in enumerate(peaks):
+        for pu in truth.get("pulses", []):
+            a0 = pu["t0_ms"] / t_ap
+            w = pu["width_ms"] / t_ap
+            if not (p["k0"] < a0 + w and a0 < p["k0"] + p["window_len"]):
+                continue
+            if abs(p["dm"] - pu["dm"]) > 2 * cells[3]:
+                continue
+            tau = pu["baseline_delay_us"][p["baseline"]]
+            e = np.zeros(4)
+            e[0] = (th[i, 0] - tau) / cells[0]
+            e[1] = ((th[i, 1] - tau + t_amb / 2) % t_amb - t_amb / 2) / cells[1]
+            e[2] = (th[i, 2] - pu.get("rate", 0.0)) / cells[2] if cells[2] > 0 else 0.0
+            e[3] = (th[i, 3] - pu["dm"]) / cells[3]
+            errs.append(e)
+            if p["window_len"] == int(round(w)):
+                dm_errs.append(e[3])
+            break
+    errs = np.abs(np.array(errs)) if errs else np.zeros((0, 4))
+    within = {k: round(float(np.mean(errs[:, i] < 0.05)), 3) if len(errs) else None
+              for i, k in enumerate(("sbd", "mbd", "rate", "dm"))}
+    med = {k: round(float(np.median(errs[:, i])), 4) if len(errs) else None
+           for i, k in enumerate(("sbd", "mbd", "rate", "dm"))}
+    return {
+        "peaks": n, "steps": args.refine_steps, "ms": round(1e3 * el, 3),
+        "kernel_ms": round(tim["refine_ms"], 3), "launches": tim["n_refine"],
+        "peak_steps_per_s": round(n * args.refine_steps / el, 1),
+        "power_gain_median": round(float(np.median(P / np.maximum(
+            s.refine_forward(torch.tensor(th0, dtype=torch.float64, device="cuda")).cpu().numpy(), 1e-30))), 5),
+        "grad_vs_central_diff_rel": {"median": float(np.median(fd_err)),
+                                     "p99": float(np.percentile(fd_err, 99)),
+                                     "max": float(np.max(fd_err))},
+        "pulse_peaks": int(len(errs)),
+        "within_0.05_cell": within,
+        "median_abs_err_cells": med,
+        "dm_within_0.05_cell_window_eq_width": (round(float(np.mean(np.abs(dm_errs) < 0.05)), 3)
+                                                if dm_errs else None),
+        "n_window_eq_width": len(dm_errs),
+    }
+
+
+def run_form(args, wl, V, prec, dev, truth=None):
     """Time `args.steps` full searches in one precision form; returns the
     JSON record (without the CPU baseline)."""
     import torch
@@ -129,6 +217,7 @@ def run_form(args, wl, V, prec, dev):
     n_det = len(s.candidates())
     groups = s.groups()
     n_rep = sum(1 for g in groups if g["reported"])
+    refine = refine_leg(args, wl, s, truth) if (prec == "f32" and args.refine_peaks > 0) else None
 
     # dominant kernel: the fringe search
     cells_per_unit = R * PJ * M
@@ -182,6 +271,8 @@ def run_form(args, wl, V, prec, dev):
         "detections": n_det,
         "reported_groups": n_rep,
     }
+    if refine is not None:
+        out["refine"] = refine
     del s, Vt
     torch.cuda.empty_cache()
     return out
@@ -202,6 +293,9 @@ def main():
     ap.add_argument("--only", action="store_true",
                     help="time only --precision (default: also the other forms, reported "
                          "with their speedup over it)")
+    ap.add_argument("--refine-peaks", type=int, default=1024,
+                    help="after the f32 search, refine this many top peaks (0: skip)")
+    ap.add_argument("--refine-steps", type=int, default=20)
     ap.add_argument("--copy-calibration-mb", type=int, default=0,
                     help="after the timed steps, run one plain device copy (float32 "
                          "multiply by 1) of this many MiB, to calibrate HBM counters")
@@ -229,7 +323,7 @@ def main():
                                                                    if p != args.precision]
     results = {}
     for prec in forms:
-        results[prec] = run_form(args, wl, V, prec, dev)
+        results[prec] = run_form(args, wl, V, prec, dev, truth)
     out = results[args.precision]
     if len(forms) > 1:
         base = out["value"]
