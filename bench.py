@@ -278,6 +278,100 @@ def run_form(args, wl, V, prec, dev, truth=None):
     return out
 
 
+def run_stream(args):
+    """Streaming search (chunks pushed as FP8 e4m3 with per-channel scales,
+    DM-overlap carry on the device): the pushes that fill the carry are
+    untimed; every later push completes a full chunk of segments and is
+    timed.  Reports chunks per second for the baselines searched and the
+    fraction of real time that one GPU sustains for the whole array."""
+    import numpy as np
+    import torch
+    from paper_1801_02391_amd import frbx
+    from paper_1801_02391_amd import workloads as W
+    name = "stream-45bl-16x256-600000"
+    base = W.get_workload(name)
+    chunk = base["chunk_frames"]
+    K = chunk * args.chunks
+    nb = args.baselines or 1
+    n_pulses = max(1, round(base["signal"]["pulses"]["count"] * K / base["layout"]["n_frames"]))
+    wl = W.get_workload(name, layout=dict(n_frames=K),
+                        signal=dict(pulses=dict(base["signal"]["pulses"], count=n_pulses)))
+    log(f"generating {nb} baseline(s) x {K} APs of {name}")
+    t0 = time.perf_counter()
+    V, truth = W.generate(wl, baselines=list(range(nb)))
+    lay = dict(wl["layout"], n_baselines=nb, stations=wl["layout"]["stations"][:nb])
+    srch = dict(wl["search"], precision=args.precision)
+    codes, scales = [], []
+    for i in range(args.chunks):
+        c8, sc = W.to_e4m3(np.ascontiguousarray(V[..., i * chunk:(i + 1) * chunk]))
+        codes.append(torch.from_numpy(c8).cuda())
+        scales.append(torch.from_numpy(sc).cuda())
+    del V
+    log(f"generated and encoded in {time.perf_counter() - t0:.1f} s")
+    s = frbx.Search(lay, device=0)
+    s.configure(srch)
+    seg = s.segments()
+    lmax = max(srch["windows"])
+    n_warm = min(args.chunks - 1, -(-(seg["dk_max"] + lmax) // chunk))
+    s.stream_begin(chunk)
+    N, J, P, M, R, D = lay["n_if"], lay["n_chan"], srch["sbd_pad"], srch["n_mbd"], srch["n_rate"], srch["n_dm"]
+    cells_seg = R * P * J * M
+    tim = {"fringe_ms": 0.0, "n_fringe": 0, "fringe_units": 0, "dedisperse_ms": 0.0,
+           "n_dedisperse": 0, "dedisperse_units": 0, "dedisperse_bytes": 0}
+    t_push, cells = [], 0
+    for i in range(args.chunks):
+        timed = i >= n_warm
+        s.set_timing(timed)
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        s.stream_push(codes[i], "e4m3", scales[i])
+        torch.cuda.synchronize()
+        el = time.perf_counter() - t
+        pos = s.stream_position()
+        ns = sum(pos["n_seg"])
+        log(f"push {i + 1}/{args.chunks} {'timed' if timed else 'warm-up'}: {el:.2f} s, {ns} segments per (b, d)")
+        if timed:
+            t_push.append(el)
+            cells += nb * D * ns * cells_seg
+            tt = s.timing()
+            for k in tim:
+                tim[k] += tt[k]
+    el = sum(t_push)
+    chunk_s = el / len(t_push)
+    t_chunk = chunk * lay["t_ap_ms"] * 1e-3
+    full_b = base["layout"]["n_baselines"]
+    avg = tim["fringe_ms"] / max(1, tim["n_fringe"])
+    units = tim["fringe_units"] / max(1, tim["n_fringe"])
+    if args.precision == "f32":
+        fpc, bound, peak, kern = fringe_flops_per_cell(N, J, P, M), "alu", PEAK_FP32_TFLOPS, "fringe_kernel"
+    else:
+        fpc = 8 * N * (3 if args.precision == "f16x3" else 1)
+        bound, peak, kern = "mfma", PEAK_FP16_MFMA_TFLOPS, "fringe_mfma_kernel"
+    ach = units * cells_seg * fpc / (avg * 1e-3) / 1e12 if avg > 0 else 0.0
+    d_avg = tim["dedisperse_ms"] / max(1, tim["n_dedisperse"])
+    d_gbs = tim["dedisperse_bytes"] / max(1, tim["n_dedisperse"]) / (d_avg * 1e-3) / 1e9 if d_avg > 0 else 0.0
+    n_det = len(s.candidates())
+    return {
+        "metric": "search cells/s (baseline x DM x window segment x rate x SBD x MBD)",
+        "value": cells / el, "unit": "cells/s", "n_gpus": 1, "steps": len(t_push), "warmup": n_warm,
+        "ms_per_step": 1e3 * chunk_s, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": {"f32": "f32", "f16x3": "f16x3 (MBD: 3 f16 MFMA products, f32 accumulate)",
+                  "f16": "f16 MFMA, f32 accumulate"}[args.precision] + ", input fp8 e4m3 + f32 scale",
+        "data": "synthetic",
+        "config": {"workload": name, "baselines": nb, "of_baselines": full_b, "if": N, "chan": J,
+                   "chunk_frames": chunk, "chunk_s": t_chunk, "dm_trials": D, "rate_bins": R,
+                   "sbd_bins": P * J, "mbd_bins": M, "windows": srch["windows"], "dk_max": seg["dk_max"]},
+        "stream": {"s_per_chunk": chunk_s, "chunks_per_s": 1.0 / chunk_s,
+                   "real_time_fraction_one_gpu_all_baselines": t_chunk / (chunk_s * full_b / nb),
+                   "dedisperse_gbs": round(d_gbs, 1), "dedisperse_frac_hbm": round(d_gbs / PEAK_HBM_GBS, 4),
+                   "detections_so_far": n_det},
+        "roofline": {"bound": bound, "achieved": round(ach, 3), "peak": peak, "unit": "TFLOP/s",
+                     "frac": round(ach / peak, 4), "traffic": None, "kernel": kern,
+                     "avg_launch_ms": round(avg, 4), "flops_per_cell": round(fpc, 2),
+                     "units_per_launch": units},
+    }
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -293,6 +387,12 @@ def main():
     ap.add_argument("--only", action="store_true",
                     help="time only --precision (default: also the other forms, reported "
                          "with their speedup over it)")
+    ap.add_argument("--baselines", type=int, default=0,
+                    help="search only the first n baselines (one GPU's share of a larger array)")
+    ap.add_argument("--stream", action="store_true",
+                    help="streaming run of the 45-baseline FP8 workload instead: --baselines "
+                         "of its baselines (default 1), --chunks 1 s chunks, the last two timed")
+    ap.add_argument("--chunks", type=int, default=6)
     ap.add_argument("--refine-peaks", type=int, default=1024,
                     help="after the f32 search, refine this many top peaks (0: skip)")
     ap.add_argument("--refine-steps", type=int, default=20)
@@ -310,11 +410,20 @@ def main():
     from paper_1801_02391_amd import frbx
     from paper_1801_02391_amd import workloads as W
 
+    if args.stream:
+        print(json.dumps(run_stream(args)), flush=True)
+        return
     wl = W.get_workload(args.workload)
     lay, srch = wl["layout"], wl["search"]
     log(f"generating {args.workload}")
     t0 = time.perf_counter()
-    V, truth = W.generate(wl)
+    if args.baselines and args.baselines < lay["n_baselines"]:
+        # one GPU's share of the baselines, at the workload's full shape
+        V, truth = W.generate(wl, baselines=list(range(args.baselines)))
+        wl["layout"]["n_baselines"] = args.baselines
+        wl["layout"]["stations"] = wl["layout"]["stations"][:args.baselines]
+    else:
+        V, truth = W.generate(wl)
     log(f"generated {V.nbytes / 1e9:.2f} GB in {time.perf_counter() - t0:.1f} s")
     dev = torch.device("cuda:0")
     torch.cuda.synchronize()

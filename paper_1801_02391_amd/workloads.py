@@ -87,6 +87,40 @@ _WORKLOADS = {
                                 width_ms=(1.0, 5.0), station_delay_us=0.5,
                                 snr=(6.0, 15.0), min_sep_frames=32)),
     ),
+    # Precision form: 7 stations -> 21 baselines; the VGOS band layout with
+    # 32 IFs x 128 x 0.25 MHz; 0.25 ms frames for 10 s; stored as complex32;
+    # 50 pulses.
+    "precision-21bl-32x128-40000": dict(
+        config_id=4,
+        layout=dict(n_stations=7, if_freq_mhz=_vgos_if_freqs(), n_chan=128,
+                    chan_bw_mhz=0.25, t_ap_ms=0.25, n_frames=40000),
+        search=dict(dm_lo=0.0, dm_step=6.25, n_dm=256, k_dm=4.149e6,
+                    sbd_pad=4, n_mbd=256, mbd_step_us=0.0, f_ref_fit_mhz=float("nan"),
+                    n_rate=8, rate_step=0.0, windows=[4, 8, 16, 32],
+                    threshold=3.0, n_win_min=3, n_bl_min=2),
+        signal=dict(noise=True, rfi_frac=0.05, rfi_amp=3.0,
+                    pulses=dict(kind="random", count=50, dm=(100.0, 1500.0),
+                                width_ms=(1.0, 5.0), station_delay_us=0.5,
+                                snr=(6.0, 15.0), min_sep_frames=64)),
+    ),
+    # Streaming: 10 stations -> 45 baselines; 16 IFs x 256 x 0.125 MHz at
+    # 768 MHz spacing from 2 GHz; 0.1 ms frames for 60 s, processed in 1 s
+    # chunks stored as FP8 e4m3 with a per-channel scale; 2048 DM trials on
+    # 0-3000; 10 % RFI channels; 200 pulses.
+    "stream-45bl-16x256-600000": dict(
+        config_id=5,
+        layout=dict(n_stations=10, if_freq_mhz=[2000.0 + 768.0 * n for n in range(16)], n_chan=256,
+                    chan_bw_mhz=0.125, t_ap_ms=0.1, n_frames=600000),
+        search=dict(dm_lo=0.0, dm_step=3000.0 / 2048, n_dm=2048, k_dm=4.149e6,
+                    sbd_pad=4, n_mbd=256, mbd_step_us=0.0, f_ref_fit_mhz=float("nan"),
+                    n_rate=16, rate_step=0.0, windows=[10, 20, 40],
+                    threshold=3.0, n_win_min=2, n_bl_min=2),
+        signal=dict(noise=True, rfi_frac=0.10, rfi_amp=3.0,
+                    pulses=dict(kind="random", count=200, dm=(100.0, 3000.0),
+                                width_ms=(1.0, 5.0), station_delay_us=0.5,
+                                snr=(5.0, 20.0), min_sep_frames=64)),
+        chunk_frames=10000,
+    ),
     # Paper-shaped (Sec. 3): 3 stations, 6 IFs x 32 x 0.5 MHz from 2192 MHz,
     # 1.024 ms APs, one DM trial at 26.833, windows 4..32 APs.  Shortened to
     # 20 s; periodic pulses of ~7 ms every 0.7145 s.
