@@ -27,6 +27,30 @@ PEAK_FP16_MFMA_TFLOPS = 2500.0  # MI355X dense FP16 matrix, published
 PEAK_HBM_GBS = 8000.0        # MI355X HBM3E, published
 
 
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_vgos_6bl_20000.txt")
+KERNEL_SOURCE = os.path.join(ROOT, "paper_1801_02391_amd", "csrc", "frbx_kernels.hip")
+
+
+def measured_traffic(key, workload):
+    """HBM bytes per launch of a kernel from the rocprofv3 FETCH_SIZE /
+    WRITE_SIZE summary in profiles/ (calibrated against a plain copy), or None
+    when there is none for this workload or the kernel source has changed
+    since the counters were taken."""
+    import hashlib
+    if workload != "vgos-6bl-32x64-20000" or not os.path.exists(TRAFFIC_FILE):
+        return None
+    vals = {}
+    for line in open(TRAFFIC_FILE):
+        line = line.split("#", 1)[0].strip()
+        if "=" in line:
+            k, v = (x.strip() for x in line.split("=", 1))
+            vals[k] = v
+    sha = hashlib.sha256(open(KERNEL_SOURCE, "rb").read()).hexdigest()
+    if vals.get("kernels_sha256") != sha or key not in vals:
+        return None
+    return float(vals[key])
+
+
 def log(msg):
     sys.stderr.write(f"[bench] {msg}\n")
     sys.stderr.flush()
@@ -234,8 +258,12 @@ def run_form(args, wl, V, prec, dev, truth=None):
         bound, peak, kern = "mfma", PEAK_FP16_MFMA_TFLOPS, "fringe_mfma_kernel"
     flops_launch = units_per_launch * cells_per_unit * fpc
     achieved = flops_launch / (avg_ms * 1e-3) / 1e12 if avg_ms > 0 else 0.0
+    tkey = kern if prec == "f32" else f"{kern}_{prec}"
+    traffic = measured_traffic(tkey, args.workload)
     roof = {"bound": bound, "achieved": round(achieved, 3), "peak": peak,
-            "unit": "TFLOP/s", "frac": round(achieved / peak, 4), "traffic": None,
+            "unit": "TFLOP/s", "frac": round(achieved / peak, 4),
+            "traffic": None if traffic is None else {"bytes_per_launch": traffic,
+                                                     "source": os.path.relpath(TRAFFIC_FILE, ROOT)},
             "kernel": kern, "avg_launch_ms": round(avg_ms, 4),
             "flops_per_cell": round(fpc, 2), "units_per_launch": units_per_launch}
     # dedispersion kernel against HBM: every dedispersed spectrum written
@@ -244,9 +272,12 @@ def run_form(args, wl, V, prec, dev, truth=None):
     d_avg = tim["dedisperse_ms"] / max(1, tim["n_dedisperse"])
     d_bytes = tim["dedisperse_bytes"] / max(1, tim["n_dedisperse"])
     d_gbs = d_bytes / (d_avg * 1e-3) / 1e9 if d_avg > 0 else 0.0
+    d_traffic = measured_traffic("dedisperse_kernel", args.workload)
     roof_dd = {"bound": "hbm", "achieved": round(d_gbs, 1), "peak": PEAK_HBM_GBS, "unit": "GB/s",
                "frac": round(d_gbs / PEAK_HBM_GBS, 4), "kernel": "dedisperse_kernel",
-               "avg_launch_ms": round(d_avg, 4)}
+               "avg_launch_ms": round(d_avg, 4), "algorithmic_bytes_per_launch": d_bytes,
+               "traffic": None if d_traffic is None else {"bytes_per_launch": d_traffic,
+                                                          "source": os.path.relpath(TRAFFIC_FILE, ROOT)}}
 
     out = {
         "metric": "search cells/s (baseline x DM x window segment x rate x SBD x MBD)",

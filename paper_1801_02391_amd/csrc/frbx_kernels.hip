@@ -412,18 +412,25 @@ __global__ __launch_bounds__(kBlock) void fringe_kernel(FringeArgs a) {
             const int sp = c + P * col;
             const int s = (sp + (PJ >> 1)) & (PJ - 1);
             const int32_t base = (r * PJ + s) * M + gl;
-            float cv = -1.0f;
-            int ck = 0;
-            static_for<0, MB>([&](auto kk) {
-              constexpr int kx = decltype(kk)::value;
-              constexpr int k2 = (kx + MB / 2) & (MB - 1);
-              const float v = z[k2].x * z[k2].x + z[k2].y * z[k2].y;
-              if (v > cv) {
-                cv = v;
-                ck = kx;
+            // peak key: |G|^2 with its 4 lowest mantissa bits replaced by
+            // (15 - kx), so one unsigned max keeps the value (to 2^-19
+            // relative) and the lowest MBD bin among equal values
+            unsigned kmax = 0u;
+            static_for<0, MB / 2>([&](auto kk) {
+              constexpr int ka = 2 * decltype(kk)::value, kb = ka + 1;
+              constexpr int k2a = (ka + MB / 2) & (MB - 1), k2b = (kb + MB / 2) & (MB - 1);
+              const float va = z[k2a].x * z[k2a].x + z[k2a].y * z[k2a].y;
+              const float vb = z[k2b].x * z[k2b].x + z[k2b].y * z[k2b].y;
+              const unsigned ua = (__float_as_uint(va) & 0xFFFFFFF0u) | unsigned(15 - ka);
+              const unsigned ub = (__float_as_uint(vb) & 0xFFFFFFF0u) | unsigned(15 - kb);
+              kmax = max(kmax, max(ua, ub));
+              if constexpr (DUMP) {
+                a.dump[base + MA * ka] = va;
+                a.dump[base + MA * kb] = vb;
               }
-              if constexpr (DUMP) a.dump[base + MA * kx] = v;
             });
+            const float cv = __uint_as_float(kmax & 0xFFFFFFF0u);
+            const int ck = 15 - int(kmax & 15u);
             const int32_t ci = base + MA * ck;
             if (cv > best_v || (cv == best_v && ci < best_i)) {
               best_v = cv;
