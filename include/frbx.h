@@ -302,9 +302,10 @@ frbx_status frbx_calibrate(frbx_ctx *ctx, int32_t baseline, int64_t k0, int32_t 
  * arguments in float64.  Needs input loaded with frbx_load /
  * frbx_load_f16 (not a stream); the input must stay resident.
  *
- * The ascent (frbx_refine_run) moves, per step, every coordinate in grid
- * cells z by -g/H (gradient over curvature of P in z) where H < 0, else by
- * max_step = 0.5 cell along the gradient, clipped to +-0.5 cell.  Cells:
+ * The ascent (frbx_refine_run) proposes, per step, a move of every
+ * coordinate in grid cells z of -g/H (gradient over curvature of P in z)
+ * where H < 0, else 0.5 cell along the gradient, clipped to +-0.5 cell, and
+ * takes it within a trust radius.  Cells:
  * SBD 1/(P J chan_bw), MBD the MBD grid step, rate the rate step (held when
  * the grid has one rate), DM the DM step, t one AP.  A DM step moves t by
  * -xbar per unit DM (xbar = mean of dx/dDM over the fitted points), which
@@ -323,8 +324,13 @@ frbx_status frbx_top_peaks(const frbx_ctx *ctx, int64_t n_max, frbx_candidate *o
  * buffers for n peaks are held by the context until the next begin. */
 frbx_status frbx_refine_begin(frbx_ctx *ctx, const frbx_candidate *peaks, int64_t n, double *theta0);
 
-/* n_steps ascent steps on the device (one launch each), then P at the final
- * parameters. */
+/* n_steps ascent steps on the device (one launch each) from the begun grid
+ * points, then the better of the last point and the best one with its P
+ * (so P never ends below its start).  Each step is a trust-region Newton
+ * step: a point that does not lower P below the best so far becomes the best
+ * (its proposed move stored, the radius doubled up to 0.5 cell), otherwise
+ * the radius is halved; the best point's move is taken clipped to the
+ * radius.  Repeated runs restart from the begun points. */
 frbx_status frbx_refine_run(frbx_ctx *ctx, int32_t n_steps);
 
 /* Results of frbx_refine_run: theta host [n][5], power host [n] (either may

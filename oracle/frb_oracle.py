@@ -745,33 +745,49 @@ def newton_ascent(fn, theta0, cells, xbar, steps=20, max_step=0.5):
     grid cells, theta = theta0 + cells * (A z) with A the identity except
     that a DM step moves the arrival offset by -xbar per unit DM (the time
     reference follows the mean dispersion shift, which decorrelates DM from
-    t).  Each step moves every live coordinate by -g_i / H_ii (gradient over
-    curvature of P in z) where H_ii < 0, else by max_step in the gradient's
-    direction, clipped to +-max_step; coordinates whose cell is 0 are held.
-    fn(theta) returns (P, grad[5], H[6]).  Returns (theta, P history)."""
+    t).  The proposed move of every live coordinate is -g_i / H_ii (gradient
+    over curvature of P in z) where H_ii < 0, else max_step along the
+    gradient, clipped to +-max_step; coordinates whose cell is 0 are held.
+    A trust region keeps it monotone: each evaluation that does not lower P
+    below the best so far is accepted (best point, its proposed move, radius
+    doubled up to max_step) and the move is taken clipped to the radius;
+    otherwise the radius is halved and the best point's move is retried,
+    clipped to the new radius.  After the steps the better of the last point
+    and the best one is returned.  fn(theta) returns (P, grad[5], H[6]).
+    Returns (theta, P history)."""
     theta0 = np.asarray(theta0, dtype=np.float64)
     cells = np.asarray(cells, dtype=np.float64)
     live = cells > 0
     a = -xbar * cells[3] / cells[4] if cells[4] > 0 else 0.0
-    z = np.zeros(5)
+
+    def move(base, dz):
+        d = dz.copy()
+        d[4] += a * d[3]
+        return base + cells * d
+
+    theta = theta0.copy()
+    best_t, best_p, best_s = theta0.copy(), -1.0, np.zeros(5)
+    radius = max_step
     hist = []
-
-    def theta_of(z):
-        dz = z.copy()
-        dz[4] += a * z[3]
-        return theta0 + cells * dz
-
     for _ in range(steps):
-        P, g, H = fn(theta_of(z))
+        P, g, H = fn(theta)
         hist.append(P)
-        gc = g * cells
-        gz = gc.copy()
-        gz[3] += a * gc[4]
-        hz = np.array([H[i] * cells[i] ** 2 for i in range(5)])
-        hz[3] = (H[3] * cells[3] ** 2 + 2 * a * H[5] * cells[3] * cells[4]
-                 + a * a * H[4] * cells[4] ** 2)
-        step = np.where(hz < 0, -gz / np.where(hz < 0, hz, -1.0), max_step * np.sign(gz))
-        z = z + np.where(live, np.clip(step, -max_step, max_step), 0.0)
-    theta = theta_of(z)
-    hist.append(fn(theta)[0])
+        if P >= best_p:
+            gc = g * cells
+            gz = gc.copy()
+            gz[3] += a * gc[4]
+            hz = np.array([H[i] * cells[i] ** 2 for i in range(5)])
+            hz[3] = (H[3] * cells[3] ** 2 + 2 * a * H[5] * cells[3] * cells[4]
+                     + a * a * H[4] * cells[4] ** 2)
+            st = np.where(hz < 0, -gz / np.where(hz < 0, hz, -1.0), max_step * np.sign(gz))
+            best_s = np.where(live, np.clip(st, -max_step, max_step), 0.0)
+            best_t, best_p = theta.copy(), P
+            radius = min(max_step, 2.0 * radius)
+        else:
+            radius *= 0.5
+        theta = move(best_t, np.clip(best_s, -radius, radius))
+    P = fn(theta)[0]
+    if P < best_p:
+        theta, P = best_t, best_p
+    hist.append(P)
     return theta, np.array(hist)

@@ -14,6 +14,7 @@
 #include <limits>
 #include <numeric>
 #include <string>
+#include <utility>
 #include <vector>
 
 #include "../../include/frbx.h"
@@ -129,6 +130,11 @@ struct frbx_ctx {
   size_t rpower_cap = 0;
   frbx::RefineChan *d_rchan = nullptr;
   size_t rchan_cap = 0;
+  double *d_rtb = nullptr, *d_rsb = nullptr, *d_rrad = nullptr;  // ascent state
+  size_t rtb_cap = 0, rsb_cap = 0, rrad_cap = 0;
+  float *d_rpb = nullptr;
+  size_t rpb_cap = 0;
+  std::vector<double> rtheta0;   // start points of the begun peaks [n][5]
   double rcells[5] = {0, 0, 0, 0, 0};
   double rxbar = 0.0;
   bool rdone = false, rbegun = false;
@@ -214,6 +220,10 @@ struct frbx_ctx {
     dfree(d_rtheta);
     dfree(d_rpower);
     dfree(d_rchan);
+    dfree(d_rtb);
+    dfree(d_rsb);
+    dfree(d_rrad);
+    dfree(d_rpb);
   }
 };
 
@@ -1541,6 +1551,10 @@ frbx::RefineArgs refine_args(const frbx_ctx *c) {
   for (int k = 0; k < 5; ++k) a.cells[k] = c->rcells[k];
   a.dm_t = c->rcells[4] > 0 ? -c->rxbar * c->rcells[3] / c->rcells[4] : 0.0;
   a.max_step = 0.5;
+  a.theta_best = c->d_rtb;
+  a.step_best = c->d_rsb;
+  a.p_best = c->d_rpb;
+  a.radius = c->d_rrad;
   return a;
 }
 
@@ -1616,6 +1630,10 @@ frbx_status frbx_refine_begin(frbx_ctx *c, const frbx_candidate *peaks, int64_t 
   if ((s = ensure(c, c->d_rtheta, c->rtheta_cap, nn_alloc * 5)) != FRBX_OK) return s;
   if ((s = ensure(c, c->d_rpower, c->rpower_cap, nn_alloc)) != FRBX_OK) return s;
   if ((s = ensure(c, c->d_rchan, c->rchan_cap, size_t(NJ))) != FRBX_OK) return s;
+  if ((s = ensure(c, c->d_rtb, c->rtb_cap, nn_alloc * 5)) != FRBX_OK) return s;
+  if ((s = ensure(c, c->d_rsb, c->rsb_cap, nn_alloc * 5)) != FRBX_OK) return s;
+  if ((s = ensure(c, c->d_rrad, c->rrad_cap, nn_alloc)) != FRBX_OK) return s;
+  if ((s = ensure(c, c->d_rpb, c->rpb_cap, nn_alloc)) != FRBX_OK) return s;
   if (n > 0) {
     if ((s = c->hip(hipMemcpyAsync(c->d_rseg, seg.data(), seg.size() * sizeof(frbx::RefineSeg),
                                    hipMemcpyHostToDevice, c->stream), "refine upload")) != FRBX_OK)
@@ -1631,6 +1649,7 @@ frbx_status frbx_refine_begin(frbx_ctx *c, const frbx_candidate *peaks, int64_t 
   c->rn = n;
   c->rdone = false;
   c->rbegun = true;
+  c->rtheta0 = th;
   if (theta0) std::copy(th.begin(), th.end(), theta0);
   return FRBX_OK;
 }
@@ -1641,11 +1660,30 @@ frbx_status frbx_refine_run(frbx_ctx *c, int32_t n_steps) {
   if (n_steps < 0) return c->fail(FRBX_E_INVAL, "n_steps < 0");
   c->spans.clear();
   c->ev_used = 0;
+  // every run starts from the begun grid points with a fresh ascent state
+  const size_t n = size_t(c->rn);
+  if (n > 0) {
+    const std::vector<double> zeros(n * 5, 0.0), rad(n, 0.5);
+    const std::vector<float> none(n, -1.0f);
+    const std::pair<void *, const void *> ups[] = {{c->d_rtheta, c->rtheta0.data()}, {c->d_rtb, c->rtheta0.data()},
+                                                   {c->d_rsb, zeros.data()}};
+    for (const auto &u : ups)
+      if ((s = c->hip(hipMemcpyAsync(u.first, u.second, n * 5 * sizeof(double), hipMemcpyHostToDevice, c->stream),
+                      "refine state")) != FRBX_OK)
+        return s;
+    if ((s = c->hip(hipMemcpyAsync(c->d_rrad, rad.data(), n * sizeof(double), hipMemcpyHostToDevice, c->stream),
+                    "refine state")) != FRBX_OK)
+      return s;
+    if ((s = c->hip(hipMemcpyAsync(c->d_rpb, none.data(), n * sizeof(float), hipMemcpyHostToDevice, c->stream),
+                    "refine state")) != FRBX_OK)
+      return s;
+    if ((s = c->hip(hipStreamSynchronize(c->stream), "refine state")) != FRBX_OK) return s;
+  }
   frbx::RefineArgs a = refine_args(c);
   a.theta = c->d_rtheta;
   a.power = c->d_rpower;
   for (int k = 0; k <= n_steps; ++k) {
-    const int mode = k < n_steps ? frbx::kRefineStep : frbx::kRefineForward;
+    const int mode = k < n_steps ? frbx::kRefineStep : frbx::kRefineFinal;
     const int sp = c->span_begin(3, c->rn);
     if ((s = c->hip(frbx::launch_refine(mode, a, c->stream), "refine launch")) != FRBX_OK) return s;
     c->span_end(sp);

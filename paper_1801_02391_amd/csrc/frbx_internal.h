@@ -147,7 +147,8 @@ struct RefineSeg {
   int32_t l;          // window length (APs)
   int64_t k0;         // first AP of the segment at f_ref
 };
-enum RefineMode { kRefineForward = 0, kRefineBackward = 1, kRefineCurvature = 2, kRefineStep = 3 };
+enum RefineMode { kRefineForward = 0, kRefineBackward = 1, kRefineCurvature = 2, kRefineStep = 3,
+                  kRefineFinal = 4 };
 struct RefineArgs {
   const void *vis;           // [B][NJ][row_stride] complex64, or complex32 when in_f16
   int32_t in_f16;
@@ -163,9 +164,13 @@ struct RefineArgs {
   const float *grad_power;   // [n] backward: upstream gradient
   double *grad_theta;        // [n][5] backward: grad_power * dP/dtheta
   double *curv;              // [n][6] curvature: d2P/dtheta_i^2 (5), d2P/dDM dt
+  double *theta_best;        // step / final: [n][5] best point so far
+  double *step_best;         // step: [n][5] proposed move at the best point (grid cells)
+  float *p_best;             // step / final: [n] |G| at the best point (-1: none yet)
+  double *radius;            // step: [n] trust radius (grid cells)
   double cells[5];           // step: grid cell of each parameter (0: held)
   double dm_t;               // step: arrival-offset cells moved per DM cell (-xbar c_DM / c_t)
-  double max_step;           // step: largest move per coordinate, cells
+  double max_step;           // step: largest move per coordinate and largest radius, cells
 };
 hipError_t launch_refine(int mode, const RefineArgs &a, hipStream_t s);
 

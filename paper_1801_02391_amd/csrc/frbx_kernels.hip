@@ -900,7 +900,7 @@ __device__ __forceinline__ float2 cfma(float2 acc, float2 a, float w) {
 // derivatives, from which thread 0 writes the mode's output.
 template <int MODE>
 __global__ __launch_bounds__(kBlock) void refine_kernel(RefineArgs a) {
-  constexpr int D = MODE == kRefineForward ? 0 : MODE == kRefineBackward ? 1 : 2;
+  constexpr int D = (MODE == kRefineForward || MODE == kRefineFinal) ? 0 : MODE == kRefineBackward ? 1 : 2;
   constexpr int NA = D == 0 ? 1 : D == 1 ? 6 : 12;
   const int p = blockIdx.x;
   const RefineSeg sg = a.seg[p];
@@ -997,6 +997,15 @@ __global__ __launch_bounds__(kBlock) void refine_kernel(RefineArgs a) {
   const double P = sqrt(gr[0] * gr[0] + gi[0] * gi[0]);
   if constexpr (MODE == kRefineForward) {
     a.power[p] = float(P);
+  } else if constexpr (MODE == kRefineFinal) {
+    // the better of the last point and the best one
+    const float Pf = float(P);
+    if (Pf < a.p_best[p]) {
+      for (int k = 0; k < 5; ++k) a.theta[5 * p + k] = a.theta_best[5 * p + k];
+      a.power[p] = a.p_best[p];
+    } else {
+      a.power[p] = Pf;
+    }
   } else {
     const double tp = 2.0 * M_PI, tp2 = tp * tp;
     // first derivatives: dG/dtau_s = -2 pi i sum f_j term, likewise MBD and rate
@@ -1031,25 +1040,42 @@ __global__ __launch_bounds__(kBlock) void refine_kernel(RefineArgs a) {
       if constexpr (MODE == kRefineCurvature) {
         for (int k = 0; k < 6; ++k) a.curv[6 * p + k] = h[k];
       } else {
-        // Newton step in grid cells; the DM coordinate carries the arrival
-        // offset along (dm_t offset cells per DM cell)
+        // trust-region Newton ascent in grid cells (the DM coordinate carries
+        // the arrival offset along, dm_t offset cells per DM cell): a point
+        // that does not lower |G| below the best so far becomes the best, with
+        // its proposed move (-g/H where the curvature is negative, else
+        // max_step along the gradient) and a doubled radius; otherwise the
+        // radius is halved.  The best point's move is then taken, clipped to
+        // the radius.
         const double *c = a.cells;
         const double at = a.dm_t;
-        double gz[5], hz[5];
-        for (int k = 0; k < 5; ++k) {
-          gz[k] = g[k] * c[k];
-          hz[k] = h[k] * c[k] * c[k];
+        const float Pf = float(P);
+        double *tb = a.theta_best + 5 * p, *sb = a.step_best + 5 * p;
+        double rad = a.radius[p];
+        if (Pf >= a.p_best[p]) {
+          double gz[5], hz[5];
+          for (int k = 0; k < 5; ++k) {
+            gz[k] = g[k] * c[k];
+            hz[k] = h[k] * c[k] * c[k];
+          }
+          gz[3] += at * g[4] * c[4];
+          hz[3] += 2.0 * at * h[5] * c[3] * c[4] + at * at * h[4] * c[4] * c[4];
+          for (int k = 0; k < 5; ++k) {
+            double s = hz[k] < 0.0 ? -gz[k] / hz[k] : a.max_step * double((gz[k] > 0.0) - (gz[k] < 0.0));
+            s = fmin(fmax(s, -a.max_step), a.max_step);
+            sb[k] = c[k] > 0.0 ? s : 0.0;
+            tb[k] = a.theta[5 * p + k];
+          }
+          a.p_best[p] = Pf;
+          rad = fmin(a.max_step, 2.0 * rad);
+        } else {
+          rad *= 0.5;
         }
-        gz[3] += at * g[4] * c[4];
-        hz[3] += 2.0 * at * h[5] * c[3] * c[4] + at * at * h[4] * c[4] * c[4];
+        a.radius[p] = rad;
         double st[5];
-        for (int k = 0; k < 5; ++k) {
-          double s = hz[k] < 0.0 ? -gz[k] / hz[k] : a.max_step * double((gz[k] > 0.0) - (gz[k] < 0.0));
-          s = fmin(fmax(s, -a.max_step), a.max_step);
-          st[k] = c[k] > 0.0 ? s : 0.0;
-        }
+        for (int k = 0; k < 5; ++k) st[k] = fmin(fmax(sb[k], -rad), rad);
         st[4] += at * st[3];
-        for (int k = 0; k < 5; ++k) a.theta[5 * p + k] += c[k] * st[k];
+        for (int k = 0; k < 5; ++k) a.theta[5 * p + k] = tb[k] + c[k] * st[k];
         a.power[p] = float(P);
       }
     }
@@ -1291,6 +1317,7 @@ hipError_t launch_refine(int mode, const RefineArgs &a, hipStream_t s) {
     case kRefineBackward: hipLaunchKernelGGL(refine_kernel<kRefineBackward>, dim3(a.n), dim3(kBlock), 0, s, a); break;
     case kRefineCurvature: hipLaunchKernelGGL(refine_kernel<kRefineCurvature>, dim3(a.n), dim3(kBlock), 0, s, a); break;
     case kRefineStep: hipLaunchKernelGGL(refine_kernel<kRefineStep>, dim3(a.n), dim3(kBlock), 0, s, a); break;
+    case kRefineFinal: hipLaunchKernelGGL(refine_kernel<kRefineFinal>, dim3(a.n), dim3(kBlock), 0, s, a); break;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();

@@ -224,3 +224,21 @@ def test_ascent_recovers_noise_free_boxcar_pulse_within_0p05_cell(seed):
     err[1] = ((th[1] - tau + T / 2) % T - T / 2) / cells[1]
     assert np.all(np.abs(err) < 0.05), err
     assert hist[-1] >= hist[0]
+
+
+def test_ascent_never_ends_below_its_start_on_noise():
+    """The trust region keeps the ascent monotone: on noise-only segments
+    (where curvature misleads) the final |G| is at least the start's."""
+    lay, s = _layout(), _search()
+    rng = np.random.default_rng(9)
+    N, J, K = 4, 16, 120
+    cells = O.refine_cells(lay, s)
+    xbar = O.mean_dm_shift(lay)
+    cal = np.ones((N, J), complex)
+    for trial in range(6):
+        Vb = _noise(rng, N, J, K)
+        fn = lambda th: O.relaxed_power_grad(*O.relaxed_fringe(Vb, lay, s, cal, 40, 4, th))
+        th0 = np.array([rng.uniform(-0.3, 0.3), 0.0, 0.0, rng.uniform(0, 60), 0.0])
+        th, hist = O.newton_ascent(fn, th0, cells, xbar, steps=20)
+        assert hist[-1] >= hist[0]
+        assert hist[-1] == pytest.approx(fn(th)[0], rel=1e-12)
