@@ -23,6 +23,9 @@ if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 PEAK_FP32_TFLOPS = 157.3     # MI355X vector FP32 (packed), published
+# without packed FP32 (kept out of every device code object): 256 CU x 4 SIMD
+# x 16 lanes x 2 flop (FMA) x 2.4 GHz
+PEAK_FP32_UNPACKED_TFLOPS = 78.6
 PEAK_FP16_MFMA_TFLOPS = 2500.0  # MI355X dense FP16 matrix, published
 PEAK_HBM_GBS = 8000.0        # MI355X HBM3E, published
 
@@ -238,7 +241,8 @@ def run_form(args, wl, V, prec, dev, truth=None):
         torch.cuda.synchronize()
         log(f"copy calibration: read {n * 4} B, wrote {n * 4} B")
         del src, dst
-    n_det = len(s.candidates())
+    cands = s.candidates()
+    n_det = len(cands)
     groups = s.groups()
     n_rep = sum(1 for g in groups if g["reported"])
     refine = refine_leg(args, wl, s, truth) if (prec == "f32" and args.refine_peaks > 0) else None
@@ -262,6 +266,8 @@ def run_form(args, wl, V, prec, dev, truth=None):
     traffic = measured_traffic(tkey, args.workload)
     roof = {"bound": bound, "achieved": round(achieved, 3), "peak": peak,
             "unit": "TFLOP/s", "frac": round(achieved / peak, 4),
+            **({"attainable_peak_unpacked": PEAK_FP32_UNPACKED_TFLOPS,
+                "frac_attainable": round(achieved / PEAK_FP32_UNPACKED_TFLOPS, 4)} if prec == "f32" else {}),
             "traffic": None if traffic is None else {"bytes_per_launch": traffic,
                                                      "source": os.path.relpath(TRAFFIC_FILE, ROOT)},
             "kernel": kern, "avg_launch_ms": round(avg_ms, 4),
@@ -301,6 +307,8 @@ def run_form(args, wl, V, prec, dev, truth=None):
         "roofline_dedisperse": roof_dd,
         "detections": n_det,
         "reported_groups": n_rep,
+        "_candidates": [(c["baseline"], c["dm_index"], c["window_len"], c["k0"], c["power_norm"])
+                        for c in cands],
     }
     if refine is not None:
         out["refine"] = refine
@@ -465,13 +473,26 @@ def main():
     for prec in forms:
         results[prec] = run_form(args, wl, V, prec, dev, truth)
     out = results[args.precision]
+    base_c = {c[:4]: c[4] for c in out["_candidates"]}
+    thr = srch["threshold"]
+
+    def compare(r):
+        other = {c[:4]: c[4] for c in r["_candidates"]}
+        diff = sorted(set(base_c) ^ set(other))
+        pn = [base_c.get(k, other.get(k)) for k in diff]
+        return {"identical": not diff, "only_" + args.precision: sum(1 for k in diff if k in base_c),
+                "only_this_form": sum(1 for k in diff if k in other),
+                "differing_power_norm_minus_threshold": [round(v - thr, 5) for v in pn[:8]]}
     if len(forms) > 1:
         base = out["value"]
         out["precision_forms"] = {
             p: {"value": r["value"], "ms_per_step": r["ms_per_step"], "dtype": r["dtype"],
                 "speedup_vs_" + args.precision: r["value"] / base, "roofline": r["roofline"],
-                "detections": r["detections"], "reported_groups": r["reported_groups"]}
+                "detections": r["detections"], "reported_groups": r["reported_groups"],
+                "candidates_vs_" + args.precision: compare(r)}
             for p, r in results.items() if p != args.precision}
+    for r in results.values():
+        r.pop("_candidates", None)
     if not args.no_cpu_baseline:
         log("timing the oracle on a CPU sample")
         out["cpu_baseline"] = cpu_baseline(wl, V[:1], args.cpu_seconds)
