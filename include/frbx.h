@@ -182,6 +182,14 @@ frbx_status frbx_load(frbx_ctx *ctx, const void *vis, int is_device);
  * The search reads them into float32. */
 frbx_status frbx_load_f16(frbx_ctx *ctx, const void *vis, int is_device);
 
+/* The cross spectra as OCP FP8 e4m3 (e4m3fn) byte pairs (re, im)
+ * [B][N][J][K][2] with one float32 scale per (baseline, IF, channel)
+ * [B][N][J] (value = decoded code x scale), both on the host (copied) or
+ * both on the device (read during the call).  The library decodes them
+ * exactly into a complex64 copy that it owns and searches that.  Errors as
+ * for frbx_load. */
+frbx_status frbx_load_e4m3(frbx_ctx *ctx, const void *codes, const float *scale, int is_device);
+
 /* Run the whole search on the context's stream and wait for it: dedispersion
  * and segment sums, fringe search and peak of every (baseline, DM trial,
  * window, segment), Eq. 6 statistics and threshold on the device; the

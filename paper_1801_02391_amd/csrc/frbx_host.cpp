@@ -757,6 +757,8 @@ frbx_status frbx_set_detection(frbx_ctx *c, double threshold, int32_t n_win_min,
   return FRBX_OK;
 }
 
+static frbx_status finish_load(frbx_ctx *c, size_t n_cplx, int f16);
+
 static frbx_status load_impl(frbx_ctx *c, const void *vis, int is_device, int f16) {
   if (!c) return FRBX_E_INVAL;
   if (!vis) return c->fail(FRBX_E_INVAL, "vis is NULL");
@@ -782,7 +784,11 @@ static frbx_status load_impl(frbx_ctx *c, const void *vis, int is_device, int f1
     c->d_vis = c->d_vis_own;
   }
   c->vis_f16 = f16;
-  // largest component, for the float16 operand scale of the matrix-core forms
+  return finish_load(c, n_cplx, f16);
+}
+
+// largest component, for the float16 operand scale of the matrix-core forms
+static frbx_status finish_load(frbx_ctx *c, size_t n_cplx, int f16) {
   if (!c->d_absmax && hipMalloc(reinterpret_cast<void **>(&c->d_absmax), sizeof(unsigned int)) != hipSuccess)
     return c->fail(FRBX_E_NOMEM, "device allocation failed");
   unsigned int am = 0;
@@ -799,6 +805,42 @@ static frbx_status load_impl(frbx_ctx *c, const void *vis, int is_device, int f1
 frbx_status frbx_load(frbx_ctx *c, const void *vis, int is_device) { return load_impl(c, vis, is_device, 0); }
 
 frbx_status frbx_load_f16(frbx_ctx *c, const void *vis, int is_device) { return load_impl(c, vis, is_device, 1); }
+
+frbx_status frbx_load_e4m3(frbx_ctx *c, const void *codes, const float *scale, int is_device) {
+  if (!c) return FRBX_E_INVAL;
+  if (!codes || !scale) return c->fail(FRBX_E_INVAL, "codes or scale is NULL");
+  if (hipSetDevice(c->device) != hipSuccess) return c->fail(FRBX_E_DEVICE, "hipSetDevice failed");
+  c->have = false;
+  c->loaded = false;
+  const int rows = c->B * c->N * c->J;
+  const size_t n_cplx = size_t(rows) * size_t(c->K);
+  frbx_status s;
+  const void *src = codes;
+  const float *sc = scale;
+  if (!is_device) {
+    if ((s = ensure(c, reinterpret_cast<char *&>(c->stage), c->stage_cap, n_cplx * 2)) != FRBX_OK) return s;
+    if ((s = c->hip(hipMemcpyAsync(c->stage, codes, n_cplx * 2, hipMemcpyHostToDevice, c->stream), "code upload")) != FRBX_OK)
+      return s;
+    src = c->stage;
+    dfree(c->d_scale);
+    if (hipMalloc(reinterpret_cast<void **>(&c->d_scale), size_t(rows) * sizeof(float)) != hipSuccess)
+      return c->fail(FRBX_E_NOMEM, "device allocation failed");
+    if ((s = c->hip(hipMemcpyAsync(c->d_scale, scale, size_t(rows) * sizeof(float), hipMemcpyHostToDevice, c->stream),
+                    "scale upload")) != FRBX_OK)
+      return s;
+    sc = c->d_scale;
+  }
+  // decoded exactly into an owned complex64 copy, searched like frbx_load's input
+  dfree(c->d_vis_own);
+  if (hipMalloc(&c->d_vis_own, n_cplx * sizeof(float2)) != hipSuccess)
+    return c->fail(FRBX_E_NOMEM, "device allocation for the cross spectra failed");
+  if ((s = c->hip(frbx::launch_ingest(src, FRBX_IN_E4M3, sc, c->K, rows, static_cast<float2 *>(c->d_vis_own), c->K, 0,
+                                      c->stream), "fp8 decode")) != FRBX_OK)
+    return s;
+  c->d_vis = c->d_vis_own;
+  c->vis_f16 = 0;
+  return finish_load(c, n_cplx, 0);
+}
 
 frbx_status frbx_set_precision(frbx_ctx *c, int32_t precision) {
   if (!c) return FRBX_E_INVAL;

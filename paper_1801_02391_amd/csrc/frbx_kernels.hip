@@ -818,29 +818,32 @@ __device__ __forceinline__ float fp8_e4m3(unsigned b) {
 __global__ __launch_bounds__(kBlock) void ingest_kernel(const void *src, int kind, const float *scale,
                                                         int64_t n_frames, int n_ch, float2 *dst,
                                                         int64_t dst_frames, int64_t k0) {
-  const int c = blockIdx.y;
-  const float sc = kind == 2 ? scale[c] : 1.0f;
-  float2 *d = dst + int64_t(c) * dst_frames + k0;
-  for (int64_t k = int64_t(blockIdx.x) * kBlock + threadIdx.x; k < n_frames;
-       k += int64_t(gridDim.x) * kBlock) {
-    const int64_t i = int64_t(c) * n_frames + k;
-    float2 v;
-    if (kind == 2) {
-      const unsigned short w = static_cast<const unsigned short *>(src)[i];
-      v = make_float2(fp8_e4m3(w & 255u) * sc, fp8_e4m3(w >> 8) * sc);
-    } else {
-      v = load_vis(src, i, kind == 1);
+  for (int c = blockIdx.y; c < n_ch; c += gridDim.y) {
+    const float sc = kind == 2 ? scale[c] : 1.0f;
+    float2 *d = dst + int64_t(c) * dst_frames + k0;
+    for (int64_t k = int64_t(blockIdx.x) * kBlock + threadIdx.x; k < n_frames;
+         k += int64_t(gridDim.x) * kBlock) {
+      const int64_t i = int64_t(c) * n_frames + k;
+      float2 v;
+      if (kind == 2) {
+        const unsigned short w = static_cast<const unsigned short *>(src)[i];
+        v = make_float2(fp8_e4m3(w & 255u) * sc, fp8_e4m3(w >> 8) * sc);
+      } else {
+        v = load_vis(src, i, kind == 1);
+      }
+      d[k] = v;
     }
-    d[k] = v;
   }
 }
 
-__global__ __launch_bounds__(kBlock) void carry_kernel(const float2 *src, float2 *dst, int64_t frames,
+__global__ __launch_bounds__(kBlock) void carry_kernel(const float2 *src, float2 *dst, int n_ch, int64_t frames,
                                                        int64_t from, int64_t n) {
-  const float2 *s = src + int64_t(blockIdx.y) * frames + from;
-  float2 *d = dst + int64_t(blockIdx.y) * frames;
-  for (int64_t k = int64_t(blockIdx.x) * kBlock + threadIdx.x; k < n; k += int64_t(gridDim.x) * kBlock)
-    d[k] = s[k];
+  for (int c = blockIdx.y; c < n_ch; c += gridDim.y) {
+    const float2 *s = src + int64_t(c) * frames + from;
+    float2 *d = dst + int64_t(c) * frames;
+    for (int64_t k = int64_t(blockIdx.x) * kBlock + threadIdx.x; k < n; k += int64_t(gridDim.x) * kBlock)
+      d[k] = s[k];
+  }
 }
 
 __global__ __launch_bounds__(kBlock) void absmax_kernel(const void *vis, int64_t n, int in_f16,
@@ -1285,7 +1288,8 @@ hipError_t launch_ingest(const void *src, int src_kind, const float *scale, int6
   (void)hipGetLastError();
   if (n_frames <= 0 || n_ch <= 0) return hipSuccess;
   const int64_t bx = std::min<int64_t>(64, (n_frames + kBlock - 1) / kBlock);
-  hipLaunchKernelGGL(ingest_kernel, dim3(unsigned(bx), unsigned(n_ch)), dim3(kBlock), 0, s, src, src_kind,
+  const unsigned gy = unsigned(std::min(n_ch, 65535));   // the kernel strides over the rest
+  hipLaunchKernelGGL(ingest_kernel, dim3(unsigned(bx), gy), dim3(kBlock), 0, s, src, src_kind,
                      scale, n_frames, n_ch, dst, dst_frames, k0);
   return hipGetLastError();
 }
@@ -1296,7 +1300,8 @@ hipError_t launch_carry(const float2 *src, float2 *dst, int n_ch, int64_t frames
   if (n <= 0 || n_ch <= 0) return hipSuccess;
   if (src == dst) return hipErrorInvalidValue;
   const int64_t bx = std::min<int64_t>(64, (n + kBlock - 1) / kBlock);
-  hipLaunchKernelGGL(carry_kernel, dim3(unsigned(bx), unsigned(n_ch)), dim3(kBlock), 0, s, src, dst, frames,
+  const unsigned gy = unsigned(std::min(n_ch, 65535));
+  hipLaunchKernelGGL(carry_kernel, dim3(unsigned(bx), gy), dim3(kBlock), 0, s, src, dst, n_ch, frames,
                      from, n);
   return hipGetLastError();
 }

@@ -86,6 +86,7 @@ _SIGS = {
     "frbx_stream_begin": ([_P, C.c_int64], C.c_int),
     "frbx_stream_push": ([_P, _P, C.c_int32, _P, C.c_int], C.c_int),
     "frbx_stream_position": ([_P, _P, _P, _P], C.c_int),
+    "frbx_load_e4m3": ([_P, _P, _P, C.c_int], C.c_int),
     "frbx_top_peaks": ([_P, C.c_int64, _P, C.c_int64, C.POINTER(C.c_int64)], C.c_int),
     "frbx_refine_cells": ([_P, _P, _P], C.c_int),
     "frbx_refine_begin": ([_P, _P, C.c_int64, _P], C.c_int),
@@ -273,6 +274,23 @@ class Search:
             else:
                 a = np.ascontiguousarray(vis, dtype=np.complex64)
                 self._chk(lib().frbx_load(self._h, _ptr(a), 0), "load")
+
+    def load_e4m3(self, codes, scale):
+        """codes: uint8 [B][N][J][K][2] OCP FP8 e4m3 (re, im); scale: float32
+        [B][N][J]; both torch GPU tensors (read during the call) or both numpy
+        arrays (copied).  Decoded exactly on the device and searched."""
+        torch = self._torch
+        if isinstance(codes, torch.Tensor):
+            if not (isinstance(scale, torch.Tensor) and codes.device.type == "cuda" and scale.device.type == "cuda"
+                    and codes.dtype == torch.uint8 and scale.dtype == torch.float32
+                    and codes.is_contiguous() and scale.is_contiguous()):
+                raise FrbxError(E_INVAL, "codes (uint8) and scale (float32) must be contiguous GPU tensors")
+            self._chk(lib().frbx_load_e4m3(self._h, _P(codes.data_ptr()), _P(scale.data_ptr()), 1), "load_e4m3")
+        else:
+            c = np.ascontiguousarray(codes, dtype=np.uint8)
+            sc = np.ascontiguousarray(scale, dtype=np.float32)
+            self._chk(lib().frbx_load_e4m3(self._h, _ptr(c), _ptr(sc), 0), "load_e4m3")
+        self._vis = None
 
     def run(self):
         self._chk(lib().frbx_run(self._h), "run")

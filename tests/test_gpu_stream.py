@@ -122,3 +122,22 @@ def test_stream_fp8_chunks_match_decoded_data():
     assert n > 100
     # the FP8 quantisation itself: detections of the pulses survive it
     assert any(abs(d["k0"] - 210) <= 8 for d in s.candidates())
+
+
+def test_whole_run_fp8_load_equals_the_decoded_data():
+    """frbx_load_e4m3 (device and host arrays) searches exactly the decoded
+    values: the power cube equals a run on from_e4m3's complex64 bit for bit."""
+    wl = _wl(400)
+    V, _ = W.generate(wl)
+    c8, sc = W.to_e4m3(V)
+    _, P0, I0 = _unsplit(wl, W.from_e4m3(c8, sc))
+    for dev in (True, False):
+        s = frbx.Search(wl["layout"])
+        s.configure(wl["search"])
+        if dev:
+            s.load_e4m3(torch.from_numpy(c8).cuda(), torch.from_numpy(sc).cuda())
+        else:
+            s.load_e4m3(c8, sc)
+        s.run()
+        P, I = s.power_cube()
+        assert np.array_equal(P.view(np.uint32), P0.view(np.uint32)) and np.array_equal(I, I0)
