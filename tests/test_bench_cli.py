@@ -1,0 +1,50 @@
+"""CPU checks of the benchmark's command line and the workload catalogue
+(no device needed)."""
+import json
+import os
+import subprocess
+import sys
+
+import numpy as np
+
+from paper_1801_02391_amd import workloads as W
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def test_more_than_one_gpu_is_refused_with_a_message():
+    r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "2"],
+                       capture_output=True, text=True, timeout=120)
+    assert r.returncode == 2
+    msg = json.loads(r.stdout.strip().splitlines()[-1])
+    assert "one GPU" in msg["error"]
+
+
+def test_workload_catalogue_shapes():
+    """The benchmark workloads carry the shapes they are quoted on."""
+    wl = W.get_workload("vgos-6bl-32x64-20000")
+    lay, s = wl["layout"], wl["search"]
+    assert (lay["n_baselines"], lay["n_if"], lay["n_chan"], lay["n_frames"]) == (6, 32, 64, 20000)
+    assert (s["n_dm"], s["n_rate"], s["sbd_pad"], s["n_mbd"]) == (256, 8, 4, 256)
+    wl = W.get_workload("precision-21bl-32x128-40000")
+    assert (wl["layout"]["n_baselines"], wl["layout"]["n_chan"], wl["layout"]["chan_bw_mhz"]) == (21, 128, 0.25)
+    wl = W.get_workload("stream-45bl-16x256-600000")
+    lay, s = wl["layout"], wl["search"]
+    assert (lay["n_baselines"], lay["n_if"], lay["n_chan"], lay["n_frames"]) == (45, 16, 256, 600000)
+    assert s["n_dm"] == 2048 and abs(s["dm_step"] * s["n_dm"] - 3000.0) < 1e-9 and wl["chunk_frames"] == 10000
+    # the IF lattice of every benchmark layout has distinct positions below M
+    for name in ("vgos-6bl-32x64-20000", "precision-21bl-32x128-40000", "stream-45bl-16x256-600000"):
+        f0 = np.asarray(W.get_workload(name)["layout"]["if_freq_mhz"])
+        d = f0 - f0[0]
+        g = np.gcd.reduce(np.round(d[1:] * 1000).astype(np.int64))
+        q = np.round(d * 1000 / g).astype(np.int64)
+        assert len(set(q)) == len(q) and q.max() < 256
+
+
+def test_short_stream_workload_generates_one_baseline():
+    wl = W.get_workload("stream-45bl-16x256-600000", layout=dict(n_frames=40000),
+                        signal=dict(pulses=dict(W.get_workload("stream-45bl-16x256-600000")["signal"]["pulses"],
+                                                count=3)))
+    V, truth = W.generate(wl, baselines=[0])
+    assert V.shape == (1, 16, 256, 40000) and V.dtype == np.complex64
+    assert len(truth["pulses"]) == 3
