@@ -309,6 +309,8 @@ def run_form(args, wl, V, prec, dev, truth=None):
         "reported_groups": n_rep,
         "_candidates": [(c["baseline"], c["dm_index"], c["window_len"], c["k0"], c["power_norm"])
                         for c in cands],
+        "_crossings": [(c["baseline"], c["dm_index"], c["window_index"], c["segment"], c["power_norm"])
+                       for c in s.crossings()],
     }
     if refine is not None:
         out["refine"] = refine
@@ -476,13 +478,24 @@ def main():
     base_c = {c[:4]: c[4] for c in out["_candidates"]}
     thr = srch["threshold"]
 
+    base_x = {c[:4]: c[4] for c in out["_crossings"]}
+
     def compare(r):
         other = {c[:4]: c[4] for c in r["_candidates"]}
         diff = sorted(set(base_c) ^ set(other))
         pn = [base_c.get(k, other.get(k)) for k in diff]
+        ox = {c[:4]: c[4] for c in r["_crossings"]}
+        xdiff = sorted(set(base_x) ^ set(ox))
+        xpn = [base_x.get(k, ox.get(k)) for k in xdiff]
+        common = set(base_x) & set(ox)
         return {"identical": not diff, "only_" + args.precision: sum(1 for k in diff if k in base_c),
                 "only_this_form": sum(1 for k in diff if k in other),
-                "differing_power_norm_minus_threshold": [round(v - thr, 5) for v in pn[:8]]}
+                "differing_power_norm_minus_threshold": [round(v - thr, 5) for v in pn[:8]],
+                "crossings_differing": len(xdiff),
+                "crossings_differing_max_abs_power_norm_minus_threshold":
+                    round(max((abs(v - thr) for v in xpn), default=0.0), 5),
+                "crossings_common_max_abs_power_norm_diff":
+                    round(max((abs(base_x[k] - ox[k]) for k in common), default=0.0), 6)}
     if len(forms) > 1:
         base = out["value"]
         out["precision_forms"] = {
@@ -493,6 +506,7 @@ def main():
             for p, r in results.items() if p != args.precision}
     for r in results.values():
         r.pop("_candidates", None)
+        r.pop("_crossings", None)
     if not args.no_cpu_baseline:
         log("timing the oracle on a CPU sample")
         out["cpu_baseline"] = cpu_baseline(wl, V[:1], args.cpu_seconds)
