@@ -34,6 +34,18 @@ TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_vgos_6bl_20000.txt")
 KERNEL_SOURCE = os.path.join(ROOT, "paper_1801_02391_amd", "csrc", "frbx_kernels.hip")
 
 
+def kernel_code_sha256():
+    """SHA-256 of the kernel source without its // comments and blank lines:
+    a change of code (not of commentary) invalidates measured counters."""
+    import hashlib
+    lines = []
+    for line in open(KERNEL_SOURCE):
+        code = line.split("//", 1)[0].rstrip()
+        if code:
+            lines.append(code)
+    return hashlib.sha256("\n".join(lines).encode()).hexdigest()
+
+
 def measured_traffic(key, workload):
     """HBM bytes per launch of a kernel from the rocprofv3 FETCH_SIZE /
     WRITE_SIZE summary in profiles/ (calibrated against a plain copy), or None
@@ -48,7 +60,7 @@ def measured_traffic(key, workload):
         if "=" in line:
             k, v = (x.strip() for x in line.split("=", 1))
             vals[k] = v
-    sha = hashlib.sha256(open(KERNEL_SOURCE, "rb").read()).hexdigest()
+    sha = kernel_code_sha256()
     if vals.get("kernels_sha256") != sha or key not in vals:
         return None
     return float(vals[key])

@@ -1,8 +1,10 @@
 // Host side of libfrbx: argument validation, the float64 tables of the
 // search (AP offsets of Eqs. 1-2, calibration phasors of Eq. 5, rate phasors
-// of Eq. 4, transform twiddles and the MBD lattice), orchestration of the
-// device kernels, and the host steps of Sec. 2.4.1 / Sec. 5.3 (multi-window
-// filter, best-DM merge, cross-baseline matching).
+// of Eq. 4, transform twiddles, the MBD lattice and its matrix-core
+// operands), orchestration of the device kernels (whole runs, streamed
+// chunks with the DM-overlap carry, power summation, refinement), the host
+// steps of Sec. 2.4.1 / Sec. 5.3 (multi-window filter, best-DM merge,
+// cross-baseline matching) and the Appendix A calibration extraction.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>

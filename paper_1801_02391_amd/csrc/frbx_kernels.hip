@@ -13,9 +13,23 @@
 //                      M-point MBD transform over the IF lattice for each SBD
 //                      column (two in-register passes, wave-local LDS
 //                      transpose) and keeps the peak of |G|^2.  VALU-bound.
+//   fringe_mfma_kernel the same search with the MBD transform as a
+//                      real-embedded complex GEMM on the matrix cores (float16
+//                      operands, float32 accumulation; one product, or three
+//                      of a high/low split for float32-grade results).
 //   stats_kernel       Eq. 6 and the threshold of Sec. 2.4.1 per (baseline,
 //                      DM trial, window): float64 two-pass mean / population
 //                      deviation, ordered compaction of the crossings.
+//   cube_sum_kernel    power summation over a set of baselines (Sec. 2.4.2).
+//   segment_sum_kernel a calibrator window sum for Appendix A.
+//   ingest_kernel,     streaming input: decode a chunk (complex64, complex32,
+//   carry_kernel       FP8 e4m3 x per-channel scale) behind the DM-overlap
+//                      carry, and copy the carry between the two buffers.
+//   refine_kernel      |G| of a segment at continuous delays, rate, DM and
+//                      arrival offset (Eq. 5 with the Eq. 4 rate term, frames
+//                      at the unrounded Eq. 1 shift by cubic interpolation),
+//                      its gradient and curvature, and a trust-region Newton
+//                      step of the ascent.
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
