@@ -16,12 +16,12 @@ from gpu_helpers import note
 pytestmark = pytest.mark.gpu
 
 
-def _wl(K, R=2, precision="f32"):
+def _wl(K, R=2, precision="f32", n_mbd=64):
     f0 = [3000.0 + 32.0 * n * (n + 1) / 2 for n in range(4)]
     return W.custom_workload(
         if_freq_mhz=f0, n_chan=32, chan_bw_mhz=1.0, t_ap_ms=1.0, n_frames=K, n_stations=3,
         config_id=130,
-        search=dict(dm_lo=0.0, dm_step=120.0, n_dm=3, sbd_pad=4, n_mbd=64, n_rate=R,
+        search=dict(dm_lo=0.0, dm_step=120.0, n_dm=3, sbd_pad=4, n_mbd=n_mbd, n_rate=R,
                     windows=[2, 4, 8], threshold=3.0, n_win_min=2, n_bl_min=2,
                     precision=precision),
         signal=dict(pulses=dict(kind="fixed", list=[
@@ -141,3 +141,30 @@ def test_whole_run_fp8_load_equals_the_decoded_data():
         s.run()
         P, I = s.power_cube()
         assert np.array_equal(P.view(np.uint32), P0.view(np.uint32)) and np.array_equal(I, I0)
+
+
+def test_stream_in_the_matrix_core_form_matches_the_oracle():
+    """Streaming with the f16x3 form (operand scale taken per push from the
+    buffer): every pushed segment against the oracle at the float32 bar."""
+    K, chunk = 600, 150
+    wl = _wl(K, precision="f16x3", n_mbd=256)
+    V, _ = W.generate(wl)
+    chunks = [np.ascontiguousarray(V[..., i * chunk:(i + 1) * chunk]) for i in range(K // chunk)]
+    s, got, _ = _stream(wl, chunks, chunk=chunk)
+    g = O.build_grids(wl["layout"], wl["search"])
+    N, J = wl["layout"]["n_if"], wl["layout"]["n_chan"]
+    cal = np.ones((N, J))
+    rng = np.random.default_rng(2)
+    n = 0
+    for w in range(3):
+        qs = sorted(got[w])
+        for q in rng.choice(qs, size=min(6, len(qs)), replace=False):
+            P, I = got[w][int(q)]
+            for b in range(P.shape[0]):
+                d = int(rng.integers(P.shape[1]))
+                po, io, s2 = O.search_row(V[b].astype(np.complex128), g, cal, d, w, q_list=[int(q)])
+                assert abs(P[b, d] - po[0]) / po[0] <= 1e-4
+                if (po[0] - s2[0]) / po[0] > 1e-3:
+                    assert I[b, d] == io[0]
+                n += 1
+    assert n >= 40
