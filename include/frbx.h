@@ -19,9 +19,10 @@
  *   most cap records, sets *n to the number available and returns
  *   FRBX_E_RANGE when cap < *n (cap = 0 is a size query).
  *   One context belongs to one host thread and one HIP stream.
- *   No entry point allocates device memory except frbx_create/frbx_load/
- *   frbx_run (which size their workspaces) and none frees memory the caller
- *   owns.
+ *   Device memory is allocated only by the entry points that size a
+ *   workspace (frbx_load*, frbx_run, frbx_stream_begin/push, frbx_power_sum,
+ *   frbx_refine_begin, frbx_dump_segment); it is reused across calls and
+ *   freed by frbx_destroy.  No entry point frees memory the caller owns.
  */
 #ifndef FRBX_H
 #define FRBX_H
