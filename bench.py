@@ -354,11 +354,14 @@ def run_stream(args):
     V, truth = W.generate(wl, baselines=list(range(nb)))
     lay = dict(wl["layout"], n_baselines=nb, stations=wl["layout"]["stations"][:nb])
     srch = dict(wl["search"], precision=args.precision)
-    codes, scales = [], []
+    codes, scales, plain = [], [], []
     for i in range(args.chunks):
-        c8, sc = W.to_e4m3(np.ascontiguousarray(V[..., i * chunk:(i + 1) * chunk]))
+        ci = np.ascontiguousarray(V[..., i * chunk:(i + 1) * chunk])
+        c8, sc = W.to_e4m3(ci)
         codes.append(torch.from_numpy(c8).cuda())
         scales.append(torch.from_numpy(sc).cuda())
+        if args.quant_error:
+            plain.append(ci)
     del V
     log(f"generated and encoded in {time.perf_counter() - t0:.1f} s")
     s = frbx.Search(lay, device=0)
@@ -371,7 +374,7 @@ def run_stream(args):
     cells_seg = R * P * J * M
     tim = {"fringe_ms": 0.0, "n_fringe": 0, "fringe_units": 0, "dedisperse_ms": 0.0,
            "n_dedisperse": 0, "dedisperse_units": 0, "dedisperse_bytes": 0}
-    t_push, cells = [], 0
+    t_push, cells, cubes = [], 0, []
     for i in range(args.chunks):
         timed = i >= n_warm
         s.set_timing(timed)
@@ -383,6 +386,8 @@ def run_stream(args):
         pos = s.stream_position()
         ns = sum(pos["n_seg"])
         log(f"push {i + 1}/{args.chunks} {'timed' if timed else 'warm-up'}: {el:.2f} s, {ns} segments per (b, d)")
+        if args.quant_error:
+            cubes.append((s.power_cube()[0], s.crossings()))
         if timed:
             t_push.append(el)
             cells += nb * D * ns * cells_seg
@@ -404,6 +409,7 @@ def run_stream(args):
     d_avg = tim["dedisperse_ms"] / max(1, tim["n_dedisperse"])
     d_gbs = tim["dedisperse_bytes"] / max(1, tim["n_dedisperse"]) / (d_avg * 1e-3) / 1e9 if d_avg > 0 else 0.0
     n_det = len(s.candidates())
+    quant = quantisation_error(s, lay, srch, chunk, plain, codes, scales, cubes, truth) if args.quant_error else None
     return {
         "metric": "search cells/s (baseline x DM x window segment x rate x SBD x MBD)",
         "value": cells / el, "unit": "cells/s", "n_gpus": 1, "steps": len(t_push), "warmup": n_warm,
@@ -422,7 +428,67 @@ def run_stream(args):
                      "frac": round(ach / peak, 4), "traffic": None, "kernel": kern,
                      "avg_launch_ms": round(avg, 4), "flops_per_cell": round(fpc, 2),
                      "units_per_launch": units},
+        "quantisation": quant,
     }
+
+
+def quantisation_error(s8, lay, srch, chunk, plain, codes, scales, pushed8, truth):
+    """Search the same chunks again unquantised (complex64) and compare with
+    the FP8 stream: the storage form's error in the data, in every segment's
+    peak power, in the threshold crossings and in the detections (all of
+    them, and those that overlap an injected pulse)."""
+    import numpy as np
+    import torch
+    from paper_1801_02391_amd import frbx
+    from paper_1801_02391_amd import workloads as W
+    num = den = 0.0
+    for c, c8, sc in zip(plain, codes, scales):
+        q = W.from_e4m3(c8.cpu().numpy(), sc.cpu().numpy())
+        num += float(np.sum(np.abs(q - c) ** 2))
+        den += float(np.sum(np.abs(c) ** 2))
+    s = frbx.Search(lay, device=0)
+    s.configure(srch)
+    s.stream_begin(chunk)
+    rel, x0, x8 = [], {}, {}
+    xkey = lambda x: (x["baseline"], x["dm_index"], x["window_index"], x["segment"])
+    for c, (P8, cr8) in zip(plain, pushed8):
+        s.stream_push(torch.from_numpy(c).cuda())
+        P = s.power_cube()[0]
+        ok = P > 0
+        rel.append((np.abs(P8[ok] - P[ok]) / P[ok]).ravel())
+        x0.update({xkey(x): x["power_norm"] for x in s.crossings()})
+        x8.update({xkey(x): x["power_norm"] for x in cr8})
+    rel = np.concatenate(rel)
+    thr = srch["threshold"]
+    xdiff = set(x0) ^ set(x8)
+    common = set(x0) & set(x8)
+    key = lambda d: (d["baseline"], d["dm_index"], d["window_len"], d["k0"])
+    d0, d8 = s.candidates(), s8.candidates()
+    a, b = {key(d) for d in d0}, {key(d) for d in d8}
+    t_ap = lay["t_ap_ms"]
+
+    def pulses_found(dets):
+        n = 0
+        for pu in truth.get("pulses", []):
+            a0, w = pu["t0_ms"] / t_ap, pu["width_ms"] / t_ap
+            if any(d["k0"] < a0 + w and a0 < d["k0"] + d["window_len"] for d in dets):
+                n += 1
+        return n
+    log(f"quantisation: {rel.size} segment powers, {len(x0)} / {len(x8)} crossings, "
+        f"{len(a)} / {len(b)} detections compared")
+    return {"vs": "the same chunks searched as complex64 (unquantised)",
+            "data_rel_rms": round(float(np.sqrt(num / den)), 5),
+            "power_rel_err_median": float(np.median(rel)), "power_rel_err_p99": float(np.quantile(rel, 0.99)),
+            "power_rel_err_max": float(rel.max()), "segments": int(rel.size),
+            "crossings_unquantised": len(x0), "crossings_fp8": len(x8), "crossings_differing": len(xdiff),
+            "crossings_differing_max_abs_power_norm_minus_threshold":
+                round(max((abs(x0.get(k, x8.get(k)) - thr) for k in xdiff), default=0.0), 4),
+            "crossings_common_max_abs_power_norm_diff":
+                round(max((abs(x0[k] - x8[k]) for k in common), default=0.0), 4),
+            "detections_unquantised": len(a), "detections_fp8": len(b),
+            "detections_only_unquantised": len(a - b), "detections_only_fp8": len(b - a),
+            "pulses_injected": len(truth.get("pulses", [])),
+            "pulses_found_unquantised": pulses_found(d0), "pulses_found_fp8": pulses_found(d8)}
 
 
 def main():
@@ -446,6 +512,9 @@ def main():
                     help="streaming run of the 45-baseline FP8 workload instead: --baselines "
                          "of its baselines (default 1), --chunks 1 s chunks, the last two timed")
     ap.add_argument("--chunks", type=int, default=6)
+    ap.add_argument("--quant-error", action="store_true",
+                    help="with --stream: search the chunks again unquantised and report the "
+                         "FP8 storage error in the data, the powers and the detections")
     ap.add_argument("--refine-peaks", type=int, default=1024,
                     help="after the f32 search, refine this many top peaks (0: skip)")
     ap.add_argument("--refine-steps", type=int, default=20)
