@@ -154,8 +154,11 @@ frbx_status frbx_set_detection(frbx_ctx *ctx, double threshold, int32_t n_win_mi
 
 /* Arithmetic of the fringe transform.
  *   FRBX_PREC_F32       float32 segment sums, SBD and MBD transforms on the
- *                       vector ALUs (in-register FFTs); powers exact in
- *                       float32.
+ *                       vector ALUs (in-register FFTs).  When every IF's MBD
+ *                       lattice position lies within one row of the first
+ *                       MBD pass (16 positions at n_mbd = 256) after a
+ *                       common shift, that pass is skipped (a phase factor
+ *                       on G; |G| is unchanged).
  *   FRBX_PREC_F16X3     float32 segment sums and SBD transform; the MBD
  *                       transform on the matrix cores as three float16
  *                       products (high x high + high x low + low x high of a
@@ -164,10 +167,10 @@ frbx_status frbx_set_detection(frbx_ctx *ctx, double threshold, int32_t n_win_mi
  *   FRBX_PREC_F16       as FRBX_PREC_F16X3 with one float16 product (inputs
  *                       and DFT matrix rounded once to float16).
  * The matrix-core forms need n_mbd = 256, n_chan >= 16 and n_if <= 32
- * (FRBX_E_INVAL at frbx_run otherwise); their peak power keeps 19 mantissa
- * bits of |G|^2 (the low bits carry the peak's position).  Operands are
- * scaled by a power of two chosen from the largest input component so that
- * float16 cannot overflow. */
+ * (FRBX_E_INVAL at frbx_run otherwise); their operands are scaled by a
+ * power of two chosen from the largest input component so that float16
+ * cannot overflow.  In every form the peak power keeps 19 mantissa bits of
+ * |G|^2 (the low bits carry the peak's position). */
 typedef enum { FRBX_PREC_F32 = 0, FRBX_PREC_F16X3 = 1, FRBX_PREC_F16 = 2 } frbx_precision;
 
 frbx_status frbx_set_precision(frbx_ctx *ctx, int32_t precision);

@@ -71,6 +71,7 @@ struct frbx_ctx {
   double mbd_step = 0, t_amb = 0, rate_step = 0;
   std::vector<int32_t> mbd_row;
   std::vector<int64_t> q_if;  // MBD lattice position of each IF
+  std::vector<int32_t> mbd_pos;  // compact lattice: q_if less a common shift (empty: general)
   std::vector<int> rate_off;
   int dd_group = 1;          // DM trials per staged dedispersion tile
 
@@ -85,7 +86,7 @@ struct frbx_ctx {
   int32_t *d_dk = nullptr;
   float2 *d_cal = nullptr, *d_rate = nullptr, *d_tw_sbd = nullptr, *d_pre = nullptr,
          *d_tw_mbd = nullptr;
-  int32_t *d_row = nullptr;
+  int32_t *d_row = nullptr, *d_pos = nullptr;
   float2 *d_w = nullptr;
   size_t w_cap = 0;
   int dt = 1;
@@ -210,6 +211,7 @@ struct frbx_ctx {
     dfree(d_pre);
     dfree(d_tw_mbd);
     dfree(d_row);
+    dfree(d_pos);
     dfree(d_w);
     dfree(d_power);
     dfree(d_pidx);
@@ -359,6 +361,20 @@ frbx_status prepare(frbx_ctx *c) {
   c->q_if.assign(N, 0);
   for (int qq = 0; qq < M; ++qq)
     if (c->mbd_row[qq] < N) c->q_if[c->mbd_row[qq]] = qq;
+  // Compact lattice: a common shift of the positions (a phase factor on G,
+  // |G| unchanged) that brings every IF below the row count of the first MBD
+  // pass lets the f32 kernel skip that pass.
+  c->mbd_pos.clear();
+  const int compact_rows = frbx::fringe_compact_rows(M);
+  for (int n0 = 0; n0 < N && c->mbd_pos.empty(); ++n0) {
+    std::vector<int32_t> pos(N);
+    bool fits = true;
+    for (int n = 0; n < N; ++n) {
+      pos[n] = int32_t(((c->q_if[n] - c->q_if[n0]) % M + M) % M);
+      fits = fits && pos[n] < compact_rows;
+    }
+    if (fits) c->mbd_pos = pos;
+  }
   // rate grid (Eq. 4)
   int lmax = 1;
   for (int l : c->windows) lmax = std::max(lmax, l);
@@ -417,6 +433,7 @@ frbx_status prepare(frbx_ctx *c) {
   if ((s = up(c->d_pre, pre)) != FRBX_OK) return s;
   if ((s = up(c->d_tw_mbd, tw_mbd)) != FRBX_OK) return s;
   if ((s = up(c->d_row, c->mbd_row)) != FRBX_OK) return s;
+  if ((s = up(c->d_pos, c->mbd_pos)) != FRBX_OK) return s;
   if ((s = up(c->d_cal, cal)) != FRBX_OK) return s;
   if (c->precision != FRBX_PREC_F32) {
     const int n_pass = c->precision == FRBX_PREC_F16X3 ? 3 : 1;
@@ -958,6 +975,7 @@ frbx_status device_pass(frbx_ctx *c, const PassSpec &ps, std::vector<DevCrossing
         fa.pre_sbd = c->d_pre;
         fa.tw_mbd = c->d_tw_mbd;
         fa.mbd_row = c->d_row;
+        fa.mbd_pos = c->mbd_pos.empty() ? nullptr : c->d_pos;
         fa.power = c->d_power + (size_t(b) * D + d0) * S;
         fa.pidx = c->d_pidx + (size_t(b) * D + d0) * S;
         fa.dump = nullptr;
@@ -1354,6 +1372,7 @@ frbx_status frbx_dump_segment(frbx_ctx *c, int32_t b, int32_t d, int32_t w, int6
   fa.pre_sbd = c->d_pre;
   fa.tw_mbd = c->d_tw_mbd;
   fa.mbd_row = c->d_row;
+  fa.mbd_pos = c->mbd_pos.empty() ? nullptr : c->d_pos;
   fa.dump = dev_out;
   fa.dump_dl = 0;
   fa.dump_seg = int(c->segoff[w] + q);

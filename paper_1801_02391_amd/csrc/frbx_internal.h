@@ -68,6 +68,8 @@ struct FringeArgs {
   const float2 *pre_sbd;     // [P][JA]   exp(-2 pi i i1 c / (P JA))
   const float2 *tw_mbd;      // [M]       exp(-2 pi i k / M)
   const int32_t *mbd_row;    // [M]       IF on lattice position q, N if none
+  const int32_t *mbd_pos;    // [N]       compact lattice: position of IF n less a common
+                             //           shift, all < fringe_compact_rows(M); null: general form
   float *power;              // [n_dt][seg_total] cube rows of (b, d0)
   int32_t *pidx;
   float *dump;               // non-null: one segment, |G|^2 of every cell
@@ -105,6 +107,8 @@ hipError_t launch_fringe(int n_chan, int n_mbd, const FringeArgs &a, size_t lds_
                          int grid, hipStream_t s);
 size_t fringe_lds_bytes(int n_chan, int n_mbd, int n_if, int sbd_pad);
 bool fringe_supported(int n_chan, int n_mbd, int n_if, int sbd_pad);
+// Lattice rows of the compact MBD form for n_mbd points (0 if unsupported).
+int fringe_compact_rows(int n_mbd);
 hipError_t launch_stats(const StatsArgs &a, int rows, hipStream_t s);
 
 // matrix-core fringe kernel: n_pass = 1 (float16) or 3 (float16 high/low

@@ -171,7 +171,8 @@ struct FringeShape {
   static constexpr int SG = MA * MB + 16;        // float2 per group scratch
 };
 
-// LDS plan (float2 units): X tile [(N+1)][J+1] with row N kept zero, a
+// LDS plan (float2 units): X tile [max(N+1, MB)][J+1] (rows of IFs, or of
+// lattice positions in the compact form; rows without an IF kept zero), a
 // scratch area shared by the SBD transpose and the MBD transposes, and the
 // PJ-point SBD twiddle table.
 template <int J, int M>
@@ -179,7 +180,8 @@ __host__ __device__ inline void fringe_lds_plan(int n_if, int sbd_pad, int &x_of
                                                 int &t_off, int &total) {
   using S = FringeShape<J, M>;
   const int xs = J + 1;
-  const int x_sz = (n_if + 1) * xs;
+  const int x_rows = n_if + 1 > S::MB ? n_if + 1 : S::MB;
+  const int x_sz = x_rows * xs;
   const int t_sz = n_if * S::JA * (S::JB + 1);
   const int m_sz = S::COLS * S::SG;
   const int s_sz = t_sz > m_sz ? t_sz : m_sz;
@@ -257,6 +259,42 @@ __device__ __forceinline__ void sbd_pass1(const float2 (&y)[JA], const float2 *p
   });
 }
 
+// Peak of one MBD column after the last MBD pass: lane k1 holds
+// z[k2] = G(s', k1 + MA k2) for SBD bin s' = c + P col.  The key of a cell
+// is |G|^2 with its 4 lowest mantissa bits replaced by (15 - k2), so one
+// unsigned max keeps the value (to 2^-19 relative) and the lowest MBD bin
+// among equal values; the running best keeps the lowest packed index.
+template <int M, int MA, int MB, bool DUMP>
+__device__ __forceinline__ void mbd_column_peak(const float2 (&z)[MB], int r, int c, int col, int k1,
+                                                int P, int PJ, float *dump, float &best_v,
+                                                int32_t &best_i) {
+  // shifted bins: s = (s' + PJ/2) mod PJ, m = k1 + MA ((k2 + MB/2) mod MB)
+  const int sp = c + P * col;
+  const int s = (sp + (PJ >> 1)) & (PJ - 1);
+  const int32_t base = (r * PJ + s) * M + k1;
+  unsigned kmax = 0u;
+  static_for<0, MB / 2>([&](auto kk) {
+    constexpr int ka = 2 * decltype(kk)::value, kb = ka + 1;
+    constexpr int k2a = (ka + MB / 2) & (MB - 1), k2b = (kb + MB / 2) & (MB - 1);
+    const float va = z[k2a].x * z[k2a].x + z[k2a].y * z[k2a].y;
+    const float vb = z[k2b].x * z[k2b].x + z[k2b].y * z[k2b].y;
+    const unsigned ua = (__float_as_uint(va) & 0xFFFFFFF0u) | unsigned(15 - ka);
+    const unsigned ub = (__float_as_uint(vb) & 0xFFFFFFF0u) | unsigned(15 - kb);
+    kmax = max(kmax, max(ua, ub));
+    if constexpr (DUMP) {
+      dump[base + MA * ka] = va;
+      dump[base + MA * kb] = vb;
+    }
+  });
+  const float cv = __uint_as_float(kmax & 0xFFFFFFF0u);
+  const int ck = 15 - int(kmax & 15u);
+  const int32_t ci = base + MA * ck;
+  if (cv > best_v || (cv == best_v && ci < best_i)) {
+    best_v = cv;
+    best_i = ci;
+  }
+}
+
 // ---------------------------------------------------------------- kernels
 __device__ __forceinline__ float2 load_vis(const void *p, int64_t i, bool f16) {
   if (f16) {
@@ -316,7 +354,13 @@ __global__ __launch_bounds__(kBlock) void dedisperse_kernel(DedisperseArgs a) {
   }
 }
 
-template <int J, int M, bool DUMP>
+// CL (compact lattice): every IF sits at a lattice position below MB once
+// the positions are shifted by a common offset (which changes only the phase
+// of G, not |G|).  The first MBD pass then has one non-zero input per lane
+// and reduces to the identity: X holds one row per position, and each lane
+// of the second pass reads the MB rows of its column directly, twiddles them
+// and transforms; the first pass and its LDS transpose drop out.
+template <int J, int M, bool DUMP, bool CL>
 __global__ __launch_bounds__(kBlock) void fringe_kernel(FringeArgs a) {
   using S = FringeShape<J, M>;
   constexpr int JA = S::JA, JB = S::JB, MA = S::MA, MB = S::MB, G = S::G, COLS = S::COLS;
@@ -349,15 +393,26 @@ __global__ __launch_bounds__(kBlock) void fringe_kernel(FringeArgs a) {
   constexpr int XS = J + 1;
 
   for (int i = t; i < PJ; i += kBlock) TW[i] = a.tw_sbd[i];
-  for (int i = t; i < XS; i += kBlock) X[N * XS + i] = make_float2(0.f, 0.f);
+  {
+    const int x_rows = N + 1 > MB ? N + 1 : MB;
+    for (int i = t; i < x_rows * XS; i += kBlock) X[i] = make_float2(0.f, 0.f);
+  }
 
   // ---- per-lane constants of the MBD transform
   const int grp = t / G, gl = t - grp * G;
   const bool m_p1 = gl < MB;  // pass-1 lane: lattice residue i2 = gl
   const bool m_p2 = gl < MA;  // pass-2 lane: output residue k1 = gl
-  float2 twm[MA];
-  int rowoff[MA];
-  if (m_p1) {
+  constexpr int NT = CL ? MB : MA;
+  float2 twm[NT];   // general: w_M^(i2 k1) for k1 < MA; compact: w_M^(i2 k1) for i2 < MB
+  int rowoff[CL ? 1 : MA];
+  if constexpr (CL) {
+    if (m_p2) {
+      static_for<0, MB>([&](auto i) {
+        constexpr int ii = decltype(i)::value;
+        twm[ii] = a.tw_mbd[(gl * ii) & (M - 1)];
+      });
+    }
+  } else if (m_p1) {
     static_for<0, MA>([&](auto k) {
       constexpr int kk = decltype(k)::value;
       twm[kk] = a.tw_mbd[(gl * kk) & (M - 1)];
@@ -391,67 +446,58 @@ __global__ __launch_bounds__(kBlock) void fringe_kernel(FringeArgs a) {
           z[ii] = Sc[(n2 * JA + k1) * (JB + 1) + ii];
         });
         dft<JB>(z);
+        const int xrow = CL ? a.mbd_pos[n2] : n2;
         static_for<0, JB>([&](auto k) {
           constexpr int kk = decltype(k)::value;
-          X[n2 * XS + k1 + JA * kk] = z[kk];
+          X[xrow * XS + k1 + JA * kk] = z[kk];
         });
       }
       __syncthreads();
 
-      // MBD over the IF lattice, one column a of this SBD tile per group.
-      for (int a0 = 0; a0 < J; a0 += COLS) {
-        const int col = a0 + grp;
-        if (col < J) {
-          if (m_p1) {
-            float2 x[MA];
-            static_for<0, MA>([&](auto i) {
-              constexpr int ii = decltype(i)::value;
-              x[ii] = X[rowoff[ii] + col];
-            });
-            dft<MA>(x);
-            static_for<0, MA>([&](auto k) {
-              constexpr int kk = decltype(k)::value;
-              Sg[kk * MB + (gl ^ (kk & (MB - 1)))] = cmul(x[kk], twm[kk]);
-            });
-          }
-          wave_lds_sync();
-          if (m_p2) {
+      if constexpr (CL) {
+        // compact lattice: z[i2] = X(position i2) w_M^(i2 k1), MB-point DFT
+        for (int a0 = 0; a0 < J; a0 += COLS) {
+          const int col = a0 + grp;
+          if (col < J && m_p2) {
             float2 z[MB];
-            static_for<0, MB>([&](auto i) {
+            z[0] = X[col];
+            static_for<1, MB>([&](auto i) {
               constexpr int ii = decltype(i)::value;
-              z[ii] = Sg[gl * MB + (ii ^ (gl & (MB - 1)))];
+              z[ii] = cmul(X[ii * XS + col], twm[ii]);
             });
             dft<MB>(z);
-            // shifted bins: s = (s' + PJ/2) mod PJ, m = gl + MA ((k2 + MB/2) mod MB)
-            const int sp = c + P * col;
-            const int s = (sp + (PJ >> 1)) & (PJ - 1);
-            const int32_t base = (r * PJ + s) * M + gl;
-            // peak key: |G|^2 with its 4 lowest mantissa bits replaced by
-            // (15 - kx), so one unsigned max keeps the value (to 2^-19
-            // relative) and the lowest MBD bin among equal values
-            unsigned kmax = 0u;
-            static_for<0, MB / 2>([&](auto kk) {
-              constexpr int ka = 2 * decltype(kk)::value, kb = ka + 1;
-              constexpr int k2a = (ka + MB / 2) & (MB - 1), k2b = (kb + MB / 2) & (MB - 1);
-              const float va = z[k2a].x * z[k2a].x + z[k2a].y * z[k2a].y;
-              const float vb = z[k2b].x * z[k2b].x + z[k2b].y * z[k2b].y;
-              const unsigned ua = (__float_as_uint(va) & 0xFFFFFFF0u) | unsigned(15 - ka);
-              const unsigned ub = (__float_as_uint(vb) & 0xFFFFFFF0u) | unsigned(15 - kb);
-              kmax = max(kmax, max(ua, ub));
-              if constexpr (DUMP) {
-                a.dump[base + MA * ka] = va;
-                a.dump[base + MA * kb] = vb;
-              }
-            });
-            const float cv = __uint_as_float(kmax & 0xFFFFFFF0u);
-            const int ck = 15 - int(kmax & 15u);
-            const int32_t ci = base + MA * ck;
-            if (cv > best_v || (cv == best_v && ci < best_i)) {
-              best_v = cv;
-              best_i = ci;
-            }
+            mbd_column_peak<M, MA, MB, DUMP>(z, r, c, col, gl, P, PJ, a.dump, best_v, best_i);
           }
-          wave_lds_sync();
+        }
+      } else {
+        // MBD over the IF lattice, one column a of this SBD tile per group.
+        for (int a0 = 0; a0 < J; a0 += COLS) {
+          const int col = a0 + grp;
+          if (col < J) {
+            if (m_p1) {
+              float2 x[MA];
+              static_for<0, MA>([&](auto i) {
+                constexpr int ii = decltype(i)::value;
+                x[ii] = X[rowoff[ii] + col];
+              });
+              dft<MA>(x);
+              static_for<0, MA>([&](auto k) {
+                constexpr int kk = decltype(k)::value;
+                Sg[kk * MB + (gl ^ (kk & (MB - 1)))] = cmul(x[kk], twm[kk]);
+              });
+            }
+            wave_lds_sync();
+            if (m_p2) {
+              float2 z[MB];
+              static_for<0, MB>([&](auto i) {
+                constexpr int ii = decltype(i)::value;
+                z[ii] = Sg[gl * MB + (ii ^ (gl & (MB - 1)))];
+              });
+              dft<MB>(z);
+              mbd_column_peak<M, MA, MB, DUMP>(z, r, c, col, gl, P, PJ, a.dump, best_v, best_i);
+            }
+            wave_lds_sync();
+          }
         }
       }
     }
@@ -1114,16 +1160,16 @@ hipError_t launch_dedisperse(const DedisperseArgs &a, hipStream_t s) {
   return hipGetLastError();
 }
 
-template <int J, int M, bool DUMP>
+template <int J, int M, bool DUMP, bool CL>
 static hipError_t launch_fringe_t(const FringeArgs &a, size_t lds, int grid, hipStream_t s) {
   (void)hipGetLastError();  // start from a clean error state
   if (lds > 64 * 1024) {
     const hipError_t e =
-        hipFuncSetAttribute(reinterpret_cast<const void *>(&fringe_kernel<J, M, DUMP>),
+        hipFuncSetAttribute(reinterpret_cast<const void *>(&fringe_kernel<J, M, DUMP, CL>),
                             hipFuncAttributeMaxDynamicSharedMemorySize, int(lds));
     if (e != hipSuccess) return e;
   }
-  hipLaunchKernelGGL((fringe_kernel<J, M, DUMP>), dim3(grid), dim3(kBlock), lds, s, a);
+  hipLaunchKernelGGL((fringe_kernel<J, M, DUMP, CL>), dim3(grid), dim3(kBlock), lds, s, a);
   return hipGetLastError();
 }
 
@@ -1156,8 +1202,11 @@ struct LaunchFn {
   int grid;
   hipStream_t s;
   template <int J, int M> hipError_t operator()() {
-    return a.dump ? launch_fringe_t<J, M, true>(a, lds, grid, s)
-                  : launch_fringe_t<J, M, false>(a, lds, grid, s);
+    if (a.mbd_pos)
+      return a.dump ? launch_fringe_t<J, M, true, true>(a, lds, grid, s)
+                    : launch_fringe_t<J, M, false, true>(a, lds, grid, s);
+    return a.dump ? launch_fringe_t<J, M, true, false>(a, lds, grid, s)
+                  : launch_fringe_t<J, M, false, false>(a, lds, grid, s);
   }
   hipError_t fail() { return hipErrorInvalidValue; }
 };
@@ -1194,6 +1243,17 @@ size_t fringe_lds_bytes(int n_chan, int n_mbd, int n_if, int sbd_pad) {
 
 bool fringe_supported(int n_chan, int n_mbd, int n_if, int sbd_pad) {
   return dispatch(n_chan, n_mbd, SupportFn{n_if, sbd_pad});
+}
+
+int fringe_compact_rows(int n_mbd) {
+  switch (n_mbd) {
+    case 16: return Split<16>::B;
+    case 32: return Split<32>::B;
+    case 64: return Split<64>::B;
+    case 128: return Split<128>::B;
+    case 256: return Split<256>::B;
+    default: return 0;
+  }
 }
 
 hipError_t launch_stats(const StatsArgs &a, int rows, hipStream_t s) {

@@ -198,3 +198,47 @@ def test_single_baseline_workload():
     best = max(gpu["candidates"], key=lambda c: c["power_norm"])
     assert best["dm_index"] == 32 and abs(best["k0"] - 400) <= 2
     assert O.wrapped_diff(best["mbd_us"], 0.020, ora["grids"]["t_amb"]) == pytest.approx(0, abs=2e-3)
+
+
+LATTICES = {  # IF sky frequencies (MHz) on a 16 MHz lattice; J = 32, M = 256
+    "compact-wrapped": [3000.0, 2984.0, 3016.0, 2968.0, 3032.0, 2952.0],  # q = 0, -1, 1, -2, 2, -3
+    "compact-edge": [3000.0, 3240.0, 3016.0],                               # q = 0, 15, 1
+    "general-edge": [3000.0, 3256.0, 3016.0],                               # q = 0, 16, 1
+    "general-spread": [3000.0, 3016.0, 3512.0, 3048.0],                     # q = 0, 1, 32, 3
+}
+
+
+@pytest.mark.parametrize("name", list(LATTICES))
+def test_compact_and_general_mbd_lattices(name):
+    """The MBD transform takes a one-pass form when every IF's lattice
+    position fits in one row of the first pass after a common shift (the
+    shift is a phase factor on G); both forms against the oracle: power cube
+    and indices, and the full |G|^2 grid of one segment."""
+    f0 = LATTICES[name]
+    J, M = 32, 256
+    wl = W.custom_workload(if_freq_mhz=f0, n_chan=J, chan_bw_mhz=1.0, t_ap_ms=1.0, n_frames=200,
+                           n_stations=2, config_id=90 + len(f0),
+                           search=dict(dm_lo=0.0, dm_step=80.0, n_dm=2, sbd_pad=4, n_mbd=M, n_rate=2,
+                                       windows=[2, 5], threshold=3.0, n_win_min=2, n_bl_min=1),
+                           signal=dict(pulses=dict(kind="fixed", list=[
+                               dict(t0_ms=90.0, dm=80.0, width_ms=4.0, snr=20.0, delay_us=0.03)])))
+    V, _ = W.generate(wl)
+    gpu = run_gpu(wl, V)
+    ora = O.search(V, wl["layout"], wl["search"])
+    segs = ora["grids"]["segs"]
+    Po, Io, S2o = oracle_cube(ora, 1, 2, segs)
+    # (few IFs on a narrow lattice give broad MBD peaks: most margins are
+    # small, so the dumped segment's peak cell is checked against the grid)
+    compare_powers(gpu["P"], gpu["I"], Po, Io, S2o, name)
+    g = ora["grids"]
+    l, h, Q = g["segs"][1]
+    q = Q // 2
+    note(f"dump {name} q={q}")
+    grid = gpu["search"].dump_segment(0, 1, 1, q)
+    rph = O.rate_phasor(g["rates"], g["f0"], l, g["t_ap"])
+    Y = O.segment_sums(V[0], g["dk"][1], [q * h], l, rph, np.ones((len(f0), J)))
+    G = np.abs(O.fringe_matrix(Y, g["e_sbd"], g["e_mbd"])[0]) ** 2
+    assert grid.shape == G.shape
+    assert np.abs(grid - G).max() / G.max() < 2e-5
+    idx = int(gpu["I"][0, 1, g["segs"][0][2] + q])
+    assert G.ravel()[idx] >= G.max() * (1 - 2e-4)
