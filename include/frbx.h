@@ -207,6 +207,15 @@ frbx_status frbx_run(frbx_ctx *ctx);
 frbx_status frbx_get_segments(const frbx_ctx *ctx, int64_t *dk_max, int32_t *hop,
                               int64_t *n_seg, int64_t *cube_len);
 
+/* MBD lattice of the Eq. 5 MBD term for the current grids: q[n] (array of N,
+ * may be NULL) = the lattice position of IF n, ((f0^n - f0^0) mbd_step M)
+ * mod M; *mbd_step_us the MBD grid step (may be NULL); *compact_shift (may
+ * be NULL) = the common shift s with every (q[n] - s) mod M inside one row
+ * of the first MBD pass, for which the float32 transform runs in one pass,
+ * or -1 when it runs the general two-pass form. */
+frbx_status frbx_get_lattice(const frbx_ctx *ctx, int64_t *q, double *mbd_step_us,
+                             int32_t *compact_shift);
+
 /* AP offsets of Eq. 2 for the current DM grid: [D][N][J] int32 (host). */
 frbx_status frbx_get_ap_offsets(const frbx_ctx *ctx, int32_t *out, int64_t cap, int64_t *n);
 

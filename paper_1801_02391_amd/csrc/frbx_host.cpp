@@ -72,6 +72,7 @@ struct frbx_ctx {
   std::vector<int32_t> mbd_row;
   std::vector<int64_t> q_if;  // MBD lattice position of each IF
   std::vector<int32_t> mbd_pos;  // compact lattice: q_if less a common shift (empty: general)
+  int32_t mbd_shift = -1;        // that shift, -1 for the general form
   std::vector<int> rate_off;
   int dd_group = 1;          // DM trials per staged dedispersion tile
 
@@ -365,6 +366,7 @@ frbx_status prepare(frbx_ctx *c) {
   // |G| unchanged) that brings every IF below the row count of the first MBD
   // pass lets the f32 kernel skip that pass.
   c->mbd_pos.clear();
+  c->mbd_shift = -1;
   const int compact_rows = frbx::fringe_compact_rows(M);
   for (int n0 = 0; n0 < N && c->mbd_pos.empty(); ++n0) {
     std::vector<int32_t> pos(N);
@@ -373,7 +375,10 @@ frbx_status prepare(frbx_ctx *c) {
       pos[n] = int32_t(((c->q_if[n] - c->q_if[n0]) % M + M) % M);
       fits = fits && pos[n] < compact_rows;
     }
-    if (fits) c->mbd_pos = pos;
+    if (fits) {
+      c->mbd_pos = pos;
+      c->mbd_shift = int32_t(c->q_if[n0]);
+    }
   }
   // rate grid (Eq. 4)
   int lmax = 1;
@@ -1261,6 +1266,18 @@ frbx_status frbx_get_segments(const frbx_ctx *cc, int64_t *dk_max, int32_t *hop,
     if (n_seg) n_seg[w] = c->nseg[w];
   }
   if (cube_len) *cube_len = c->seg_total;
+  return FRBX_OK;
+}
+
+frbx_status frbx_get_lattice(const frbx_ctx *cc, int64_t *q, double *mbd_step_us, int32_t *compact_shift) {
+  frbx_ctx *c = const_cast<frbx_ctx *>(cc);
+  if (!c) return FRBX_E_INVAL;
+  frbx_status s = prepare(c);
+  if (s != FRBX_OK) return s;
+  if (q)
+    for (int n = 0; n < c->N; ++n) q[n] = c->q_if[n];
+  if (mbd_step_us) *mbd_step_us = c->mbd_step;
+  if (compact_shift) *compact_shift = c->mbd_shift;
   return FRBX_OK;
 }
 

@@ -74,6 +74,7 @@ _SIGS = {
     "frbx_set_precision": ([_P, C.c_int32], C.c_int),
     "frbx_run": ([_P], C.c_int),
     "frbx_get_segments": ([_P, _P, _P, _P, _P], C.c_int),
+    "frbx_get_lattice": ([_P, _P, _P, _P], C.c_int),
     "frbx_get_ap_offsets": ([_P, _P, C.c_int64, _P], C.c_int),
     "frbx_get_power_cube": ([_P, _P, _P, C.c_int64, _P], C.c_int),
     "frbx_get_power_cube_device": ([_P, _P, _P], C.c_int),
@@ -305,6 +306,16 @@ class Search:
         self._chk(lib().frbx_get_segments(self._h, C.byref(dkm), _ptr(hop), _ptr(nseg),
                                           C.byref(tot)), "get_segments")
         return dict(dk_max=dkm.value, hop=hop.tolist(), n_seg=nseg.tolist(), total=tot.value)
+
+    def lattice(self):
+        """MBD lattice positions of the IFs, the MBD step (us) and the shift
+        of the compact one-pass form of the float32 transform (-1: general)."""
+        q = np.zeros(self.layout["n_if"], dtype=np.int64)
+        step = C.c_double(0.0)
+        shift = C.c_int32(0)
+        self._chk(lib().frbx_get_lattice(self._h, _ptr(q), C.byref(step), C.byref(shift)),
+                  "get_lattice")
+        return dict(q=q.tolist(), mbd_step_us=step.value, compact_shift=shift.value)
 
     def ap_offsets(self):
         n = C.c_int64(0)

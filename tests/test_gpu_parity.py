@@ -225,6 +225,15 @@ def test_compact_and_general_mbd_lattices(name):
     V, _ = W.generate(wl)
     gpu = run_gpu(wl, V)
     ora = O.search(V, wl["layout"], wl["search"])
+    lat = gpu["search"].lattice()
+    t_amb = ora["grids"]["t_amb"]
+    assert lat["mbd_step_us"] == pytest.approx(t_amb / M, rel=1e-12)
+    q = [round((f - f0[0]) * t_amb) % M for f in f0]
+    assert lat["q"] == q
+    if name.startswith("compact"):
+        assert lat["compact_shift"] in q and max((x - lat["compact_shift"]) % M for x in q) < 16
+    else:
+        assert lat["compact_shift"] == -1
     segs = ora["grids"]["segs"]
     Po, Io, S2o = oracle_cube(ora, 1, 2, segs)
     # (few IFs on a narrow lattice give broad MBD peaks: most margins are
