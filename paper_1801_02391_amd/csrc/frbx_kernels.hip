@@ -171,16 +171,17 @@ struct FringeShape {
   static constexpr int SG = MA * MB + 16;        // float2 per group scratch
 };
 
-// LDS plan (float2 units): X tile [max(N+1, MB)][J+1] (rows of IFs, or of
-// lattice positions in the compact form; rows without an IF kept zero), a
-// scratch area shared by the SBD transpose and the MBD transposes, and the
-// PJ-point SBD twiddle table.
-template <int J, int M>
+// LDS plan (float2 units): X tile [N+1][J+1] (rows of IFs, the last kept
+// zero), or [max(N+1, MB)][J+1] in the compact form (rows of lattice
+// positions, those without an IF kept zero), a scratch area shared by the
+// SBD transpose and the MBD transposes, and the PJ-point SBD twiddle table.
+// The host sizes the launch with the larger plan (CL = true).
+template <int J, int M, bool CL = true>
 __host__ __device__ inline void fringe_lds_plan(int n_if, int sbd_pad, int &x_off, int &s_off,
                                                 int &t_off, int &total) {
   using S = FringeShape<J, M>;
   const int xs = J + 1;
-  const int x_rows = n_if + 1 > S::MB ? n_if + 1 : S::MB;
+  const int x_rows = CL && S::MB > n_if + 1 ? S::MB : n_if + 1;
   const int x_sz = x_rows * xs;
   const int t_sz = n_if * S::JA * (S::JB + 1);
   const int m_sz = S::COLS * S::SG;
@@ -386,16 +387,19 @@ __global__ __launch_bounds__(kBlock) void fringe_kernel(FringeArgs a) {
   const float2 *rph = a.rate_ph + a.rate_off[wi];
 
   int x_off, s_off, t_off, total;
-  fringe_lds_plan<J, M>(N, P, x_off, s_off, t_off, total);
+  fringe_lds_plan<J, M, CL>(N, P, x_off, s_off, t_off, total);
   float2 *X = lds + x_off;
   float2 *Sc = lds + s_off;
   float2 *TW = lds + t_off;
   constexpr int XS = J + 1;
 
   for (int i = t; i < PJ; i += kBlock) TW[i] = a.tw_sbd[i];
-  {
-    const int x_rows = N + 1 > MB ? N + 1 : MB;
-    for (int i = t; i < x_rows * XS; i += kBlock) X[i] = make_float2(0.f, 0.f);
+  if constexpr (CL) {
+    // rows of lattice positions without an IF stay zero
+    for (int i = t; i < MB * XS; i += kBlock) X[i] = make_float2(0.f, 0.f);
+  } else {
+    // the zero row read for empty lattice points
+    for (int i = t; i < XS; i += kBlock) X[N * XS + i] = make_float2(0.f, 0.f);
   }
 
   // ---- per-lane constants of the MBD transform
