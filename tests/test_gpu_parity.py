@@ -200,11 +200,14 @@ def test_single_baseline_workload():
     assert O.wrapped_diff(best["mbd_us"], 0.020, ora["grids"]["t_amb"]) == pytest.approx(0, abs=2e-3)
 
 
-LATTICES = {  # IF sky frequencies (MHz) on a 16 MHz lattice; J = 32, M = 256
-    "compact-wrapped": [3000.0, 2984.0, 3016.0, 2968.0, 3032.0, 2952.0],  # q = 0, -1, 1, -2, 2, -3
-    "compact-edge": [3000.0, 3240.0, 3016.0],                               # q = 0, 15, 1
-    "general-edge": [3000.0, 3256.0, 3016.0],                               # q = 0, 16, 1
-    "general-spread": [3000.0, 3016.0, 3512.0, 3048.0],                     # q = 0, 1, 32, 3
+LATTICES = {  # (IF sky frequencies in MHz on a 16 MHz lattice, M); J = 32
+    # first-pass rows: 16 positions at M = 256, 8 at M = 128
+    "compact-wrapped": ([3000.0, 2984.0, 3016.0, 2968.0, 3032.0, 2952.0], 256),  # q = 0, -1, 1, -2, 2, -3
+    "compact-edge": ([3000.0, 3240.0, 3016.0], 256),                               # q = 0, 15, 1
+    "general-edge": ([3000.0, 3256.0, 3016.0], 256),                               # q = 0, 16, 1
+    "general-spread": ([3000.0, 3016.0, 3512.0, 3048.0], 256),                     # q = 0, 1, 32, 3
+    "compact-edge-m128": ([3000.0, 3016.0, 3112.0], 128),                          # q = 0, 1, 7
+    "general-edge-m128": ([3000.0, 3016.0, 3128.0], 128),                          # q = 0, 1, 8
 }
 
 
@@ -214,8 +217,9 @@ def test_compact_and_general_mbd_lattices(name):
     position fits in one row of the first pass after a common shift (the
     shift is a phase factor on G); both forms against the oracle: power cube
     and indices, and the full |G|^2 grid of one segment."""
-    f0 = LATTICES[name]
-    J, M = 32, 256
+    f0, M = LATTICES[name]
+    J = 32
+    rows = 16 if M == 256 else 8
     wl = W.custom_workload(if_freq_mhz=f0, n_chan=J, chan_bw_mhz=1.0, t_ap_ms=1.0, n_frames=200,
                            n_stations=2, config_id=90 + len(f0),
                            search=dict(dm_lo=0.0, dm_step=80.0, n_dm=2, sbd_pad=4, n_mbd=M, n_rate=2,
@@ -231,7 +235,7 @@ def test_compact_and_general_mbd_lattices(name):
     q = [round((f - f0[0]) * t_amb) % M for f in f0]
     assert lat["q"] == q
     if name.startswith("compact"):
-        assert lat["compact_shift"] in q and max((x - lat["compact_shift"]) % M for x in q) < 16
+        assert lat["compact_shift"] in q and max((x - lat["compact_shift"]) % M for x in q) < rows
     else:
         assert lat["compact_shift"] == -1
     segs = ora["grids"]["segs"]
