@@ -123,7 +123,41 @@ def cpu_baseline(wl, V, target_s=15.0):
     return {"value": cells / el, "unit": "cells/s", "cores": int(threads), "kind": "oracle",
             "sample": f"{n} segments (window {g['segs'][0][0]} APs, baseline 0, DM trial {d}) "
                       f"x {R} rates x {PJ} SBD x {M} MBD cells, float64 numpy oracle, "
-                      f"{el:.1f} s"}
+                      f"{el:.1f} s",
+            **host_cpu()}
+
+
+def host_cpu():
+    """The host's CPU model and logical core count."""
+    model = ""
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                model = line.split(":", 1)[1].strip()
+                break
+    except OSError:
+        pass
+    return {"cpu_model": model, "host_logical_cores": os.cpu_count()}
+
+
+def cpu_full(wl, V, gpu_candidates):
+    """The FP64 oracle over the whole workload (every baseline, DM trial,
+    window and segment), timed, and its single-pulse detections against the
+    f32 search's (baseline, DM trial, window, first AP) on the same data."""
+    from oracle import frb_oracle as O
+    lay, srch = wl["layout"], wl["search"]
+    g = O.build_grids(lay, srch)
+    t0 = time.perf_counter()
+    res = O.search(V, lay, srch)
+    el = time.perf_counter() - t0
+    cells = lay["n_baselines"] * srch["n_dm"] * sum(q for (_, _, q) in g["segs"]) * \
+        len(g["rates"]) * len(g["tau_s"]) * len(g["tau_m"])
+    ora = {(d["b"], d["d"], d["l"], d["k0"]) for d in res["detections"]}
+    gpu = {c[:4] for c in gpu_candidates}
+    return {"value": cells / el, "unit": "cells/s", "seconds": round(el, 2), "cells": cells,
+            "kind": "oracle, whole workload", "detections_oracle": len(ora),
+            "detections_identical": ora == gpu, "only_oracle": len(ora - gpu),
+            "only_gpu": len(gpu - ora), **host_cpu()}
 
 
 def refine_leg(args, wl, s, truth):
@@ -514,6 +548,9 @@ def main():
     ap.add_argument("--workload", default="vgos-6bl-32x64-20000")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--cpu-full", action="store_true",
+                    help="also run the FP64 oracle over the whole workload (small workloads): "
+                         "its cells/s and whether its detections equal the f32 search's")
     ap.add_argument("--precision", default="f32", choices=["f32", "f16x3", "f16"],
                     help="f32: vector-ALU FFT transforms; f16x3: MBD on the matrix cores "
                          "as three float16 products (float32-grade); f16: one float16 "
@@ -600,6 +637,9 @@ def main():
                 "detections": r["detections"], "reported_groups": r["reported_groups"],
                 "candidates_vs_" + args.precision: compare(r)}
             for p, r in results.items() if p != args.precision}
+    if args.cpu_full and args.precision == "f32":
+        log("timing the oracle on the whole workload")
+        out["cpu_full"] = cpu_full(wl, V, out["_candidates"])
     for r in results.values():
         r.pop("_candidates", None)
         r.pop("_crossings", None)
