@@ -16,8 +16,10 @@ from gpu_helpers import note
 pytestmark = pytest.mark.gpu
 
 
-def _wl(K, R=2, precision="f32", n_mbd=64):
-    f0 = [3000.0 + 32.0 * n * (n + 1) / 2 for n in range(4)]
+def _wl(K, R=2, precision="f32", n_mbd=64, n_if=4):
+    # lattice positions 0, 1, 3, 6 (within the 8 first-pass rows of M = 64:
+    # the one-pass MBD form), or with n_if = 5 also 10 (the two-pass form)
+    f0 = [3000.0 + 32.0 * n * (n + 1) / 2 for n in range(n_if)]
     return W.custom_workload(
         if_freq_mhz=f0, n_chan=32, chan_bw_mhz=1.0, t_ap_ms=1.0, n_frames=K, n_stations=3,
         config_id=130,
@@ -63,10 +65,10 @@ def _stream(wl, chunks, kind="c64", scales=None, chunk=None):
     return s, got, stats
 
 
-@pytest.mark.parametrize("chunk", [150, 97])
-def test_stream_matches_unsplit_bitwise(chunk):
+@pytest.mark.parametrize("chunk,n_if", [(150, 4), (97, 4), (97, 5)])
+def test_stream_matches_unsplit_bitwise(chunk, n_if):
     K = 600
-    wl = _wl(K)
+    wl = _wl(K, n_if=n_if)
     V, _ = W.generate(wl)
     s0, P0, I0 = _unsplit(wl, V)
     seg = s0.segments()
