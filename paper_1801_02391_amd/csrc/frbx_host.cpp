@@ -72,6 +72,10 @@ struct frbx_ctx {
   std::vector<int32_t> mbd_row;
   std::vector<int64_t> q_if;  // MBD lattice position of each IF
   std::vector<int32_t> mbd_pos;  // compact lattice: q_if less a common shift (empty: general)
+  double recheck_band = 0.0;     // matrix-core forms: re-evaluate |P_norm - threshold| < band
+  int64_t n_rechecked = 0;       // segments re-evaluated by the last pass
+  int32_t *d_list = nullptr;     // their (DM trial, segment) list
+  size_t list_cap = 0;
   int32_t mbd_shift = -1;        // that shift, -1 for the general form
   std::vector<int> rate_off;
   int dd_group = 1;          // DM trials per staged dedispersion tile
@@ -213,6 +217,7 @@ struct frbx_ctx {
     dfree(d_tw_mbd);
     dfree(d_row);
     dfree(d_pos);
+    dfree(d_list);
     dfree(d_w);
     dfree(d_power);
     dfree(d_pidx);
@@ -876,6 +881,21 @@ frbx_status frbx_set_precision(frbx_ctx *c, int32_t precision) {
   return FRBX_OK;
 }
 
+frbx_status frbx_set_recheck(frbx_ctx *c, double band) {
+  if (!c) return FRBX_E_INVAL;
+  if (!(band >= 0.0)) return c->fail(FRBX_E_INVAL, "recheck band must be >= 0");
+  c->recheck_band = band;
+  c->have = false;
+  return FRBX_OK;
+}
+
+frbx_status frbx_get_recheck(const frbx_ctx *c, double *band, int64_t *n_last) {
+  if (!c) return FRBX_E_INVAL;
+  if (band) *band = c->recheck_band;
+  if (n_last) *n_last = c->n_rechecked;
+  return FRBX_OK;
+}
+
 }  // extern "C"
 
 namespace {
@@ -894,6 +914,123 @@ struct PassSpec {
   std::vector<int> k0, nq, off;
   int64_t S;
 };
+
+// Eq. 6 statistics of every (baseline, DM trial, window) row and the
+// segments whose normalised power exceeds `thr` (unordered) into `hc`.
+frbx_status stats_pass(frbx_ctx *c, frbx::StatsArgs &st, size_t rows, int64_t S, double thr,
+                       std::vector<DevCrossing> &hc) {
+  frbx_status s;
+  st.threshold = thr;
+  st.out = c->d_cross;
+  st.cap = c->cross_cap;
+  unsigned long long ncr = 0;
+  for (int attempt = 0; attempt < 2; ++attempt) {
+    if ((s = c->hip(hipMemsetAsync(c->d_ncross, 0, sizeof(unsigned long long), c->stream), "memset")) != FRBX_OK)
+      return s;
+    const int sp = S > 0 ? c->span_begin(2, int64_t(rows)) : -1;
+    if (S > 0 && (s = c->hip(frbx::launch_stats(st, int(rows), c->stream), "stats launch")) != FRBX_OK) return s;
+    c->span_end(sp);
+    if ((s = c->hip(hipMemcpyAsync(&ncr, c->d_ncross, sizeof(ncr), hipMemcpyDeviceToHost, c->stream),
+                    "crossing count")) != FRBX_OK)
+      return s;
+    if ((s = c->hip(hipStreamSynchronize(c->stream), "search")) != FRBX_OK) return s;
+    if (int64_t(ncr) <= c->cross_cap) break;
+    dfree(c->d_cross);
+    c->cross_cap = 0;
+    if (hipMalloc(reinterpret_cast<void **>(&c->d_cross), size_t(ncr) * sizeof(DevCrossing)) != hipSuccess)
+      return c->fail(FRBX_E_NOMEM, "device allocation for crossings failed");
+    c->cross_cap = int64_t(ncr);
+    st.out = c->d_cross;
+    st.cap = c->cross_cap;
+  }
+  hc.assign(ncr, DevCrossing{});
+  if (ncr && (s = c->hip(hipMemcpy(hc.data(), c->d_cross, ncr * sizeof(DevCrossing), hipMemcpyDeviceToHost),
+                         "crossings copy")) != FRBX_OK)
+    return s;
+  return FRBX_OK;
+}
+
+// Re-evaluation of near-threshold segments after a matrix-core pass: the
+// segments with |P_norm - threshold| < band (normalised with this pass's
+// statistics) are searched again by the float32 kernel, one (baseline, DM
+// trial) at a time after dedispersing that trial alone; their powers and
+// indices in the cube are replaced.
+frbx_status recheck_pass(frbx_ctx *c, const PassSpec &ps, frbx::StatsArgs &st, size_t rows,
+                         int64_t k_eff) {
+  frbx_status s;
+  const int D = c->n_dm, NJ = c->N * c->J, nw = int(c->windows.size()), J = c->J, M = c->n_mbd;
+  const int64_t S = ps.S;
+  if (!frbx::fringe_supported(J, M, c->N, c->sbd_pad))
+    return c->fail(FRBX_E_INVAL, "recheck needs a shape the float32 search supports");
+  std::vector<DevCrossing> near;
+  if ((s = stats_pass(c, st, rows, S, c->threshold - c->recheck_band, near)) != FRBX_OK) return s;
+  // (b * D + d) -> segments of that row pair, as (0, cube segment) pairs
+  std::vector<std::pair<int32_t, int32_t>> sel;
+  for (const DevCrossing &x : near)
+    if (x.pnorm < c->threshold + c->recheck_band) sel.emplace_back(x.row / nw, ps.off[x.row % nw] + x.q);
+  std::sort(sel.begin(), sel.end());
+  c->n_rechecked = int64_t(sel.size());
+  if (sel.empty()) return FRBX_OK;
+  std::vector<int32_t> list(sel.size() * 2);
+  for (size_t i = 0; i < sel.size(); ++i) {
+    list[2 * i] = 0;
+    list[2 * i + 1] = sel[i].second;
+  }
+  if ((s = ensure(c, c->d_list, c->list_cap, list.size())) != FRBX_OK) return s;
+  if ((s = c->hip(hipMemcpy(c->d_list, list.data(), list.size() * sizeof(int32_t), hipMemcpyHostToDevice),
+                  "list upload")) != FRBX_OK)
+    return s;
+  const size_t lds = frbx::fringe_lds_bytes(J, M, c->N, c->sbd_pad);
+  const size_t in_bytes = ps.vis_f16 ? 4 : 8;
+  for (size_t i0 = 0; i0 < sel.size();) {
+    size_t i1 = i0;
+    while (i1 < sel.size() && sel[i1].first == sel[i0].first) ++i1;
+    const int bd = sel[i0].first, b = bd / D, d = bd % D;
+    frbx::DedisperseArgs da{};
+    da.vis = static_cast<const char *>(ps.vis) + size_t(b) * NJ * size_t(ps.stride) * in_bytes;
+    da.in_f16 = ps.vis_f16;
+    da.n_frames = ps.K;
+    da.row_stride = ps.stride;
+    da.dk = c->d_dk;
+    da.d0 = d;
+    da.n_dt = 1;
+    da.cal = c->d_cal + size_t(b) * NJ;
+    da.out = c->d_w;
+    da.k_eff = k_eff;
+    da.nj = NJ;
+    da.group = 1;
+    if ((s = c->hip(frbx::launch_dedisperse(da, c->stream), "dedisperse launch")) != FRBX_OK) return s;
+    frbx::FringeArgs fa{};
+    fa.w = c->d_w;
+    fa.w_dm_stride = k_eff * NJ;
+    fa.n_if = c->N;
+    fa.n_rate = c->n_rate;
+    fa.sbd_pad = c->sbd_pad;
+    fa.n_win = nw;
+    for (int w = 0; w < nw; ++w) {
+      fa.win_len[w] = c->windows[w];
+      fa.win_hop[w] = c->hop[w];
+      fa.win_off[w] = ps.off[w];
+      fa.win_k0[w] = ps.k0[w];
+      fa.rate_off[w] = c->rate_off[w];
+    }
+    fa.seg_total = int(S);
+    fa.n_dt = 1;
+    fa.rate_ph = c->d_rate;
+    fa.tw_sbd = c->d_tw_sbd;
+    fa.pre_sbd = c->d_pre;
+    fa.tw_mbd = c->d_tw_mbd;
+    fa.mbd_row = c->d_row;
+    fa.mbd_pos = c->mbd_pos.empty() ? nullptr : c->d_pos;
+    fa.seg_list = c->d_list + 2 * i0;
+    fa.power = c->d_power + size_t(bd) * S;
+    fa.pidx = c->d_pidx + size_t(bd) * S;
+    if ((s = c->hip(frbx::launch_fringe_list(J, M, fa, lds, int(i1 - i0), c->stream), "recheck launch")) != FRBX_OK)
+      return s;
+    i0 = i1;
+  }
+  return FRBX_OK;
+}
 
 frbx_status device_pass(frbx_ctx *c, const PassSpec &ps, std::vector<DevCrossing> &hc) {
   frbx_status s;
@@ -1006,41 +1143,19 @@ frbx_status device_pass(frbx_ctx *c, const PassSpec &ps, std::vector<DevCrossing
     st.win_off[w] = ps.off[w];
     st.win_q[w] = ps.nq[w];
   }
-  st.threshold = c->threshold;
   st.mean = c->d_mean;
   st.stdev = c->d_sd;
   st.count = c->d_cnt;
-  st.out = c->d_cross;
   st.n_out = c->d_ncross;
-  st.cap = c->cross_cap;
-  unsigned long long ncr = 0;
-  for (int attempt = 0; attempt < 2; ++attempt) {
-    if ((s = c->hip(hipMemsetAsync(c->d_ncross, 0, sizeof(unsigned long long), c->stream), "memset")) != FRBX_OK)
-      return s;
-    const int sp = S > 0 ? c->span_begin(2, int64_t(rows)) : -1;
-    if (S > 0 && (s = c->hip(frbx::launch_stats(st, int(rows), c->stream), "stats launch")) != FRBX_OK) return s;
-    c->span_end(sp);
-    if ((s = c->hip(hipMemcpyAsync(&ncr, c->d_ncross, sizeof(ncr), hipMemcpyDeviceToHost, c->stream),
-                    "crossing count")) != FRBX_OK)
-      return s;
-    if ((s = c->hip(hipStreamSynchronize(c->stream), "search")) != FRBX_OK) return s;
-    if (int64_t(ncr) <= c->cross_cap) break;
-    dfree(c->d_cross);
-    c->cross_cap = 0;
-    if (hipMalloc(reinterpret_cast<void **>(&c->d_cross), size_t(ncr) * sizeof(DevCrossing)) != hipSuccess)
-      return c->fail(FRBX_E_NOMEM, "device allocation for crossings failed");
-    c->cross_cap = int64_t(ncr);
-    st.out = c->d_cross;
-    st.cap = c->cross_cap;
-  }
+  c->n_rechecked = 0;
+  if (use_mfma && c->recheck_band > 0 && S > 0 && k_eff > 0 &&
+      (s = recheck_pass(c, ps, st, rows, k_eff)) != FRBX_OK)
+    return s;
+  if ((s = stats_pass(c, st, rows, S, c->threshold, hc)) != FRBX_OK) return s;
   if (c->timing) c->collect_timing();
-  hc.assign(ncr, DevCrossing{});
   c->mean.assign(rows, 0.0);
   c->sd.assign(rows, 0.0);
   c->cnt.assign(rows, 0);
-  if (ncr && (s = c->hip(hipMemcpy(hc.data(), c->d_cross, ncr * sizeof(DevCrossing), hipMemcpyDeviceToHost),
-                         "crossings copy")) != FRBX_OK)
-    return s;
   if (rows && S > 0) {
     if ((s = c->hip(hipMemcpy(c->mean.data(), c->d_mean, rows * sizeof(double), hipMemcpyDeviceToHost), "stats")) != FRBX_OK ||
         (s = c->hip(hipMemcpy(c->sd.data(), c->d_sd, rows * sizeof(double), hipMemcpyDeviceToHost), "stats")) != FRBX_OK ||

@@ -361,7 +361,9 @@ __global__ __launch_bounds__(kBlock) void dedisperse_kernel(DedisperseArgs a) {
 // and reduces to the identity: X holds one row per position, and each lane
 // of the second pass reads the MB rows of its column directly, twiddles them
 // and transforms; the first pass and its LDS transpose drop out.
-template <int J, int M, bool DUMP, bool CL>
+// LIST: one work-group per entry of a.seg_list instead of per segment of the
+// tile (re-evaluation of selected segments).
+template <int J, int M, bool DUMP, bool CL, bool LIST = false>
 __global__ __launch_bounds__(kBlock) void fringe_kernel(FringeArgs a) {
   using S = FringeShape<J, M>;
   constexpr int JA = S::JA, JB = S::JB, MA = S::MA, MB = S::MB, G = S::G, COLS = S::COLS;
@@ -377,7 +379,12 @@ __global__ __launch_bounds__(kBlock) void fringe_kernel(FringeArgs a) {
   // ---- which segment: spread consecutive segments over the 8 XCDs in
   // contiguous ranges so that overlapping segments share an L2.
   int dl, seg;
-  block_segment(a, DUMP, dl, seg);
+  if constexpr (LIST) {
+    dl = a.seg_list[2 * blockIdx.x];
+    seg = a.seg_list[2 * blockIdx.x + 1];
+  } else {
+    block_segment(a, DUMP, dl, seg);
+  }
   int wi = 0;
   while (wi + 1 < a.n_win && a.win_off[wi + 1] <= seg) ++wi;
   const int l = a.win_len[wi];
@@ -1164,16 +1171,16 @@ hipError_t launch_dedisperse(const DedisperseArgs &a, hipStream_t s) {
   return hipGetLastError();
 }
 
-template <int J, int M, bool DUMP, bool CL>
+template <int J, int M, bool DUMP, bool CL, bool LIST = false>
 static hipError_t launch_fringe_t(const FringeArgs &a, size_t lds, int grid, hipStream_t s) {
   (void)hipGetLastError();  // start from a clean error state
   if (lds > 64 * 1024) {
     const hipError_t e =
-        hipFuncSetAttribute(reinterpret_cast<const void *>(&fringe_kernel<J, M, DUMP, CL>),
+        hipFuncSetAttribute(reinterpret_cast<const void *>(&fringe_kernel<J, M, DUMP, CL, LIST>),
                             hipFuncAttributeMaxDynamicSharedMemorySize, int(lds));
     if (e != hipSuccess) return e;
   }
-  hipLaunchKernelGGL((fringe_kernel<J, M, DUMP, CL>), dim3(grid), dim3(kBlock), lds, s, a);
+  hipLaunchKernelGGL((fringe_kernel<J, M, DUMP, CL, LIST>), dim3(grid), dim3(kBlock), lds, s, a);
   return hipGetLastError();
 }
 
@@ -1247,6 +1254,26 @@ size_t fringe_lds_bytes(int n_chan, int n_mbd, int n_if, int sbd_pad) {
 
 bool fringe_supported(int n_chan, int n_mbd, int n_if, int sbd_pad) {
   return dispatch(n_chan, n_mbd, SupportFn{n_if, sbd_pad});
+}
+
+template <int J>
+static hipError_t launch_fringe_list_t(const FringeArgs &a, size_t lds, int n, hipStream_t s) {
+  return a.mbd_pos ? launch_fringe_t<J, 256, false, true, true>(a, lds, n, s)
+                   : launch_fringe_t<J, 256, false, false, true>(a, lds, n, s);
+}
+
+hipError_t launch_fringe_list(int n_chan, int n_mbd, const FringeArgs &a, size_t lds_bytes, int n,
+                              hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  if (n_mbd != 256 || !a.seg_list || n > 2147483647) return hipErrorInvalidValue;
+  switch (n_chan) {
+    case 16: return launch_fringe_list_t<16>(a, lds_bytes, n, s);
+    case 32: return launch_fringe_list_t<32>(a, lds_bytes, n, s);
+    case 64: return launch_fringe_list_t<64>(a, lds_bytes, n, s);
+    case 128: return launch_fringe_list_t<128>(a, lds_bytes, n, s);
+    case 256: return launch_fringe_list_t<256>(a, lds_bytes, n, s);
+    default: return hipErrorInvalidValue;
+  }
 }
 
 int fringe_compact_rows(int n_mbd) {

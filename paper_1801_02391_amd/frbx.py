@@ -75,6 +75,8 @@ _SIGS = {
     "frbx_run": ([_P], C.c_int),
     "frbx_get_segments": ([_P, _P, _P, _P, _P], C.c_int),
     "frbx_get_lattice": ([_P, _P, _P, _P], C.c_int),
+    "frbx_set_recheck": ([_P, C.c_double], C.c_int),
+    "frbx_get_recheck": ([_P, _P, _P], C.c_int),
     "frbx_get_ap_offsets": ([_P, _P, C.c_int64, _P], C.c_int),
     "frbx_get_power_cube": ([_P, _P, _P, C.c_int64, _P], C.c_int),
     "frbx_get_power_cube_device": ([_P, _P, _P], C.c_int),
@@ -247,6 +249,7 @@ class Search:
         prec = search.get("precision", "f32")
         self._chk(L.frbx_set_precision(h, PRECISIONS[prec] if isinstance(prec, str) else int(prec)),
                   "set_precision")
+        self._chk(L.frbx_set_recheck(h, float(search.get("recheck_band", 0.0))), "set_recheck")
         if tau0_us is not None or phi0_rad is not None:
             t = None if tau0_us is None else np.ascontiguousarray(tau0_us, dtype=np.float64)
             p = None if phi0_rad is None else np.ascontiguousarray(phi0_rad, dtype=np.float64)
@@ -306,6 +309,13 @@ class Search:
         self._chk(lib().frbx_get_segments(self._h, C.byref(dkm), _ptr(hop), _ptr(nseg),
                                           C.byref(tot)), "get_segments")
         return dict(dk_max=dkm.value, hop=hop.tolist(), n_seg=nseg.tolist(), total=tot.value)
+
+    def recheck(self):
+        """(band, segments re-evaluated in float32 by the last run or push)."""
+        band = C.c_double(0.0)
+        n = C.c_int64(0)
+        self._chk(lib().frbx_get_recheck(self._h, C.byref(band), C.byref(n)), "get_recheck")
+        return band.value, n.value
 
     def lattice(self):
         """MBD lattice positions of the IFs, the MBD step (us) and the shift

@@ -129,6 +129,8 @@ def test_invalid_arguments_are_rejected_without_a_device():
     assert L.frbx_get_candidates(None, None, 0, C.byref(n)) == frbx.E_INVAL
     assert L.frbx_run(None) == frbx.E_INVAL
     assert L.frbx_get_lattice(None, None, None, None) == frbx.E_INVAL
+    assert L.frbx_set_recheck(None, 0.05) == frbx.E_INVAL
+    assert L.frbx_get_recheck(None, None, None) == frbx.E_INVAL
     # the refinement entry points refuse a NULL context
     assert L.frbx_top_peaks(None, 5, None, 0, C.byref(n)) == frbx.E_INVAL
     assert L.frbx_refine_begin(None, None, 0, None) == frbx.E_INVAL
