@@ -259,8 +259,11 @@ def run_form(args, wl, V, prec, dev, truth=None):
     from paper_1801_02391_amd import frbx
     from paper_1801_02391_amd import workloads as W
     lay = wl["layout"]
-    srch = dict(wl["search"], precision=prec)
-    if prec == "f16":
+    # "f16-recheck": the f16 form with near-threshold segments re-evaluated in f32
+    base_prec = "f16" if prec == "f16-recheck" else prec
+    band = args.recheck_band if prec == "f16-recheck" else 0.0
+    srch = dict(wl["search"], precision=base_prec, recheck_band=band)
+    if base_prec == "f16":
         Vt = torch.from_numpy(W.to_complex32(V)).to(dev)
     else:
         Vt = torch.from_numpy(V).to(dev)
@@ -325,7 +328,7 @@ def run_form(args, wl, V, prec, dev, truth=None):
         bound, peak, kern = "mfma", PEAK_FP16_MFMA_TFLOPS, "fringe_mfma_kernel"
     flops_launch = units_per_launch * cells_per_unit * fpc
     achieved = flops_launch / (avg_ms * 1e-3) / 1e12 if avg_ms > 0 else 0.0
-    tkey = kern if prec == "f32" else f"{kern}_{prec}"
+    tkey = kern if prec == "f32" else f"{kern}_{base_prec}"
     traffic = measured_traffic(tkey, args.workload)
     roof = {"bound": bound, "achieved": round(achieved, 3), "peak": peak,
             "unit": "TFLOP/s", "frac": round(achieved / peak, 4),
@@ -343,7 +346,7 @@ def run_form(args, wl, V, prec, dev, truth=None):
     d_avg = tim["dedisperse_ms"] / max(1, tim["n_dedisperse"])
     d_bytes = tim["dedisperse_bytes"] / max(1, tim["n_dedisperse"])
     d_gbs = d_bytes / (d_avg * 1e-3) / 1e9 if d_avg > 0 else 0.0
-    d_traffic = measured_traffic("dedisperse_kernel_complex32" if prec == "f16" else "dedisperse_kernel",
+    d_traffic = measured_traffic("dedisperse_kernel_complex32" if base_prec == "f16" else "dedisperse_kernel",
                                  args.workload)
     roof_dd = {"bound": "hbm", "achieved": round(d_gbs, 1), "peak": PEAK_HBM_GBS, "unit": "GB/s",
                "frac": round(d_gbs / PEAK_HBM_GBS, 4), "kernel": "dedisperse_kernel",
@@ -363,7 +366,9 @@ def run_form(args, wl, V, prec, dev, truth=None):
         "scaling": "weak",
         "vs_baseline": None,
         "dtype": {"f32": "f32", "f16x3": "f16x3 (MBD: 3 f16 MFMA products, f32 accumulate)",
-                  "f16": "f16 storage + f16 MFMA, f32 accumulate"}[prec],
+                  "f16": "f16 storage + f16 MFMA, f32 accumulate",
+                  "f16-recheck": f"f16 storage + f16 MFMA, f32 accumulate; segments within "
+                                 f"{band} of the threshold re-evaluated in f32"}[prec],
         "data": "synthetic",
         "config": {"workload": args.workload, "baselines": B, "if": N, "chan": J,
                    "frames": lay["n_frames"], "dm_trials": D, "rate_bins": R, "sbd_bins": PJ,
@@ -371,6 +376,9 @@ def run_form(args, wl, V, prec, dev, truth=None):
                    "cells_per_step": cells},
         "roofline": roof,
         "roofline_dedisperse": roof_dd,
+        **({"recheck": {"band": band, "segments": s.recheck()[1],
+                        "fraction_of_segments": s.recheck()[1] / max(1, B * D * seg["total"])}}
+           if band > 0 else {}),
         "detections": n_det,
         "reported_groups": n_rep,
         "_candidates": [(c["baseline"], c["dm_index"], c["window_len"], c["k0"], c["power_norm"])
@@ -569,6 +577,9 @@ def main():
                     help="streaming run of the 45-baseline FP8 workload instead: --baselines "
                          "of its baselines (default 1), --chunks 1 s chunks, the last two timed")
     ap.add_argument("--chunks", type=int, default=6)
+    ap.add_argument("--recheck-band", type=float, default=0.05,
+                    help="band around the threshold (in normalised power) re-evaluated in f32 "
+                         "by the f16-recheck form")
     ap.add_argument("--quant-error", action="store_true",
                     help="with --stream: search the chunks again unquantised and report the "
                          "FP8 storage error in the data, the powers and the detections")
@@ -607,7 +618,7 @@ def main():
     dev = torch.device("cuda:0")
     torch.cuda.synchronize()
 
-    forms = [args.precision] if args.only else [args.precision] + [p for p in ("f16x3", "f16")
+    forms = [args.precision] if args.only else [args.precision] + [p for p in ("f16x3", "f16", "f16-recheck")
                                                                    if p != args.precision]
     results = {}
     for prec in forms:
@@ -640,6 +651,7 @@ def main():
             p: {"value": r["value"], "ms_per_step": r["ms_per_step"], "dtype": r["dtype"],
                 "speedup_vs_" + args.precision: r["value"] / base, "roofline": r["roofline"],
                 "detections": r["detections"], "reported_groups": r["reported_groups"],
+                **({"recheck": r["recheck"]} if "recheck" in r else {}),
                 "candidates_vs_" + args.precision: compare(r)}
             for p, r in results.items() if p != args.precision}
     if args.cpu_full and args.precision == "f32":

@@ -180,9 +180,9 @@ frbx_status frbx_set_precision(frbx_ctx *ctx, int32_t precision);
  * band > 0, after the search in FRBX_PREC_F16X3 or FRBX_PREC_F16 (frbx_run
  * or frbx_stream_push), every segment whose Eq. 6 normalised power lies
  * within `band` of the threshold is searched again by the float32 kernel
- * (its DM trial dedispersed again on its own), its power and index are
- * replaced in the cube, and the statistics, crossings and detections are
- * taken from the updated cube.  band = 0 (default) turns it off; ignored in
+ * (its segment sums gathered straight from the input with the AP offsets),
+ * its power and index are replaced in the cube, and the statistics,
+ * crossings and detections are taken from the updated cube.  band = 0 (default) turns it off; ignored in
  * FRBX_PREC_F32; FRBX_E_INVAL for band < 0, and at frbx_run for a shape the
  * float32 search does not support. */
 frbx_status frbx_set_recheck(frbx_ctx *ctx, double band);

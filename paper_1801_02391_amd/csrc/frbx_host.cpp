@@ -952,11 +952,10 @@ frbx_status stats_pass(frbx_ctx *c, frbx::StatsArgs &st, size_t rows, int64_t S,
 
 // Re-evaluation of near-threshold segments after a matrix-core pass: the
 // segments with |P_norm - threshold| < band (normalised with this pass's
-// statistics) are searched again by the float32 kernel, one (baseline, DM
-// trial) at a time after dedispersing that trial alone; their powers and
-// indices in the cube are replaced.
-frbx_status recheck_pass(frbx_ctx *c, const PassSpec &ps, frbx::StatsArgs &st, size_t rows,
-                         int64_t k_eff) {
+// statistics) are searched again by the float32 kernel in one launch (one
+// work-group per segment, the segment sums gathered straight from the
+// input); their powers and indices in the cube are replaced.
+frbx_status recheck_pass(frbx_ctx *c, const PassSpec &ps, frbx::StatsArgs &st, size_t rows) {
   frbx_status s;
   const int D = c->n_dm, NJ = c->N * c->J, nw = int(c->windows.size()), J = c->J, M = c->n_mbd;
   const int64_t S = ps.S;
@@ -964,72 +963,54 @@ frbx_status recheck_pass(frbx_ctx *c, const PassSpec &ps, frbx::StatsArgs &st, s
     return c->fail(FRBX_E_INVAL, "recheck needs a shape the float32 search supports");
   std::vector<DevCrossing> near;
   if ((s = stats_pass(c, st, rows, S, c->threshold - c->recheck_band, near)) != FRBX_OK) return s;
-  // (b * D + d) -> segments of that row pair, as (0, cube segment) pairs
-  std::vector<std::pair<int32_t, int32_t>> sel;
-  for (const DevCrossing &x : near)
-    if (x.pnorm < c->threshold + c->recheck_band) sel.emplace_back(x.row / nw, ps.off[x.row % nw] + x.q);
-  std::sort(sel.begin(), sel.end());
-  c->n_rechecked = int64_t(sel.size());
-  if (sel.empty()) return FRBX_OK;
-  std::vector<int32_t> list(sel.size() * 2);
-  for (size_t i = 0; i < sel.size(); ++i) {
-    list[2 * i] = 0;
-    list[2 * i + 1] = sel[i].second;
+  std::vector<int32_t> list;
+  for (const DevCrossing &x : near) {
+    if (!(x.pnorm < c->threshold + c->recheck_band)) continue;
+    const int bd = x.row / nw;
+    list.push_back(bd / D);
+    list.push_back(bd % D);
+    list.push_back(int32_t(ps.off[x.row % nw] + x.q));
   }
+  const int64_t n = int64_t(list.size() / 3);
+  c->n_rechecked = n;
+  if (n == 0) return FRBX_OK;
+  if (n > 2147483647) return c->fail(FRBX_E_INVAL, "too many segments to re-evaluate");
   if ((s = ensure(c, c->d_list, c->list_cap, list.size())) != FRBX_OK) return s;
   if ((s = c->hip(hipMemcpy(c->d_list, list.data(), list.size() * sizeof(int32_t), hipMemcpyHostToDevice),
                   "list upload")) != FRBX_OK)
     return s;
-  const size_t lds = frbx::fringe_lds_bytes(J, M, c->N, c->sbd_pad);
-  const size_t in_bytes = ps.vis_f16 ? 4 : 8;
-  for (size_t i0 = 0; i0 < sel.size();) {
-    size_t i1 = i0;
-    while (i1 < sel.size() && sel[i1].first == sel[i0].first) ++i1;
-    const int bd = sel[i0].first, b = bd / D, d = bd % D;
-    frbx::DedisperseArgs da{};
-    da.vis = static_cast<const char *>(ps.vis) + size_t(b) * NJ * size_t(ps.stride) * in_bytes;
-    da.in_f16 = ps.vis_f16;
-    da.n_frames = ps.K;
-    da.row_stride = ps.stride;
-    da.dk = c->d_dk;
-    da.d0 = d;
-    da.n_dt = 1;
-    da.cal = c->d_cal + size_t(b) * NJ;
-    da.out = c->d_w;
-    da.k_eff = k_eff;
-    da.nj = NJ;
-    da.group = 1;
-    if ((s = c->hip(frbx::launch_dedisperse(da, c->stream), "dedisperse launch")) != FRBX_OK) return s;
-    frbx::FringeArgs fa{};
-    fa.w = c->d_w;
-    fa.w_dm_stride = k_eff * NJ;
-    fa.n_if = c->N;
-    fa.n_rate = c->n_rate;
-    fa.sbd_pad = c->sbd_pad;
-    fa.n_win = nw;
-    for (int w = 0; w < nw; ++w) {
-      fa.win_len[w] = c->windows[w];
-      fa.win_hop[w] = c->hop[w];
-      fa.win_off[w] = ps.off[w];
-      fa.win_k0[w] = ps.k0[w];
-      fa.rate_off[w] = c->rate_off[w];
-    }
-    fa.seg_total = int(S);
-    fa.n_dt = 1;
-    fa.rate_ph = c->d_rate;
-    fa.tw_sbd = c->d_tw_sbd;
-    fa.pre_sbd = c->d_pre;
-    fa.tw_mbd = c->d_tw_mbd;
-    fa.mbd_row = c->d_row;
-    fa.mbd_pos = c->mbd_pos.empty() ? nullptr : c->d_pos;
-    fa.seg_list = c->d_list + 2 * i0;
-    fa.power = c->d_power + size_t(bd) * S;
-    fa.pidx = c->d_pidx + size_t(bd) * S;
-    if ((s = c->hip(frbx::launch_fringe_list(J, M, fa, lds, int(i1 - i0), c->stream), "recheck launch")) != FRBX_OK)
-      return s;
-    i0 = i1;
+  frbx::FringeArgs fa{};
+  fa.n_if = c->N;
+  fa.n_rate = c->n_rate;
+  fa.sbd_pad = c->sbd_pad;
+  fa.n_win = nw;
+  for (int w = 0; w < nw; ++w) {
+    fa.win_len[w] = c->windows[w];
+    fa.win_hop[w] = c->hop[w];
+    fa.win_off[w] = ps.off[w];
+    fa.win_k0[w] = ps.k0[w];
+    fa.rate_off[w] = c->rate_off[w];
   }
-  return FRBX_OK;
+  fa.seg_total = int(S);
+  fa.n_dt = D;
+  fa.rate_ph = c->d_rate;
+  fa.tw_sbd = c->d_tw_sbd;
+  fa.pre_sbd = c->d_pre;
+  fa.tw_mbd = c->d_tw_mbd;
+  fa.mbd_row = c->d_row;
+  fa.mbd_pos = c->mbd_pos.empty() ? nullptr : c->d_pos;
+  fa.seg_list = c->d_list;
+  fa.vis = ps.vis;
+  fa.vis_f16 = ps.vis_f16;
+  fa.n_dm = D;
+  fa.vis_stride = ps.stride;
+  fa.vis_frames = ps.K;
+  fa.dk = c->d_dk;
+  fa.cal = c->d_cal;
+  fa.power = c->d_power;
+  fa.pidx = c->d_pidx;
+  const size_t lds = frbx::fringe_lds_bytes(J, M, c->N, c->sbd_pad);
+  return c->hip(frbx::launch_fringe_list(J, M, fa, lds, int(n), c->stream), "recheck launch");
 }
 
 frbx_status device_pass(frbx_ctx *c, const PassSpec &ps, std::vector<DevCrossing> &hc) {
@@ -1148,8 +1129,7 @@ frbx_status device_pass(frbx_ctx *c, const PassSpec &ps, std::vector<DevCrossing
   st.count = c->d_cnt;
   st.n_out = c->d_ncross;
   c->n_rechecked = 0;
-  if (use_mfma && c->recheck_band > 0 && S > 0 && k_eff > 0 &&
-      (s = recheck_pass(c, ps, st, rows, k_eff)) != FRBX_OK)
+  if (use_mfma && c->recheck_band > 0 && S > 0 && k_eff > 0 && (s = recheck_pass(c, ps, st, rows)) != FRBX_OK)
     return s;
   if ((s = stats_pass(c, st, rows, S, c->threshold, hc)) != FRBX_OK) return s;
   if (c->timing) c->collect_timing();

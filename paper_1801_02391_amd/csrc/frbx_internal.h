@@ -70,7 +70,18 @@ struct FringeArgs {
   const int32_t *mbd_row;    // [M]       IF on lattice position q, N if none
   const int32_t *mbd_pos;    // [N]       compact lattice: position of IF n less a common
                              //           shift, all < fringe_compact_rows(M); null: general form
-  const int32_t *seg_list;   // list launches: [grid][2] (DM trial in the tile, segment)
+  // list launches (re-evaluation of selected segments): one work-group per
+  // (baseline, DM trial, segment) triple, the segment sums gathered straight
+  // from the input with the AP offsets (no dedispersed copy); `power` and
+  // `pidx` then point at the whole cube [B][D][seg_total]
+  const int32_t *seg_list;   // [grid][3]
+  const void *vis;           // [B][N J][vis_stride], complex64 or complex32
+  int32_t vis_f16;
+  int32_t n_dm;
+  int64_t vis_stride;        // elements per channel row
+  int64_t vis_frames;        // valid APs per row
+  const int32_t *dk;         // [D][N J] AP offsets
+  const float2 *cal;         // [B][N J] calibration phasors
   float *power;              // [n_dt][seg_total] cube rows of (b, d0)
   int32_t *pidx;
   float *dump;               // non-null: one segment, |G|^2 of every cell
@@ -110,8 +121,8 @@ size_t fringe_lds_bytes(int n_chan, int n_mbd, int n_if, int sbd_pad);
 bool fringe_supported(int n_chan, int n_mbd, int n_if, int sbd_pad);
 // Lattice rows of the compact MBD form for n_mbd points (0 if unsupported).
 int fringe_compact_rows(int n_mbd);
-// The float32 fringe search of the n segments listed in a.seg_list (one
-// work-group each), n_mbd = 256 only.
+// The float32 fringe search of the n (baseline, DM trial, segment) triples
+// listed in a.seg_list (one work-group each), n_mbd = 256 only.
 hipError_t launch_fringe_list(int n_chan, int n_mbd, const FringeArgs &a, size_t lds_bytes, int n,
                               hipStream_t s);
 hipError_t launch_stats(const StatsArgs &a, int rows, hipStream_t s);

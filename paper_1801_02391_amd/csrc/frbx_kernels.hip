@@ -242,6 +242,41 @@ __device__ __forceinline__ void segment_sum(float2 (&y)[JA], const float2 *wd, c
 
 // SBD pass 1 of tile c: x[i1] = y[i1] w_{P JA}^{i1 c}; JA-point DFT over i1;
 // twiddle w_PJ^{i2 (c + P k1)}; store transposed T[n][k1][i2].
+__device__ __forceinline__ float2 load_vis(const void *p, int64_t i, bool f16) {
+  if (f16) {
+    const _Float16 *h = static_cast<const _Float16 *>(p) + 2 * i;
+    return make_float2(float(h[0]), float(h[1]));
+  }
+  return static_cast<const float2 *>(p)[i];
+}
+
+// The same segment sum gathered straight from the input of baseline b at DM
+// trial d: W[k][c] = cal[c] V[c][k + dk[d][c]] (zero past the last AP),
+// formed and accumulated in the same order as the dedispersed path.
+template <int JA, int JB>
+__device__ __forceinline__ void segment_sum_direct(float2 (&y)[JA], const FringeArgs &a, int b, int d,
+                                                   int64_t k0, const float2 *rph, int r, int N, int J,
+                                                   int l, int R, bool act, int n1, int i2s) {
+  static_for<0, JA>([&](auto i) { y[decltype(i)::value] = make_float2(0.f, 0.f); });
+  if (!act) return;
+  const int NJ = N * J;
+  const float2 *ph = rph + (r * N + n1) * l;
+  static_for<0, JA>([&](auto i) {
+    constexpr int ii = decltype(i)::value;
+    const int c = n1 * J + JB * ii + i2s;
+    const float2 cal = a.cal[int64_t(b) * NJ + c];
+    const int64_t row = (int64_t(b) * NJ + c) * a.vis_stride;
+    const int64_t f0 = k0 + a.dk[int64_t(d) * NJ + c];
+    for (int u = 0; u < l; ++u) {
+      const int64_t f = f0 + u;
+      const float2 v = f < a.vis_frames ? load_vis(a.vis, row + f, a.vis_f16 != 0) : make_float2(0.f, 0.f);
+      const float2 w = cmul(v, cal);
+      y[ii] = R > 1 ? cadd(y[ii], cmul(w, ph[u])) : cadd(y[ii], w);
+    }
+  });
+  if (i2s == 0) y[0] = make_float2(0.f, 0.f);
+}
+
 template <int JA, int JB>
 __device__ __forceinline__ void sbd_pass1(const float2 (&y)[JA], const float2 *pre,
                                           const float2 *TW, float2 *Sc, int c, int P, int PJ,
@@ -297,13 +332,6 @@ __device__ __forceinline__ void mbd_column_peak(const float2 (&z)[MB], int r, in
 }
 
 // ---------------------------------------------------------------- kernels
-__device__ __forceinline__ float2 load_vis(const void *p, int64_t i, bool f16) {
-  if (f16) {
-    const _Float16 *h = static_cast<const _Float16 *>(p) + 2 * i;
-    return make_float2(float(h[0]), float(h[1]));
-  }
-  return static_cast<const float2 *>(p)[i];
-}
 
 // One work-group dedisperses a tile of 16 channels x 256 APs for a group of
 // DM trials: each channel's input span (the 128 APs shifted by the group's
@@ -379,9 +407,12 @@ __global__ __launch_bounds__(kBlock) void fringe_kernel(FringeArgs a) {
   // ---- which segment: spread consecutive segments over the 8 XCDs in
   // contiguous ranges so that overlapping segments share an L2.
   int dl, seg;
+  int lb = 0, ld = 0;
   if constexpr (LIST) {
-    dl = a.seg_list[2 * blockIdx.x];
-    seg = a.seg_list[2 * blockIdx.x + 1];
+    lb = a.seg_list[3 * blockIdx.x];
+    ld = a.seg_list[3 * blockIdx.x + 1];
+    seg = a.seg_list[3 * blockIdx.x + 2];
+    dl = lb * a.n_dm + ld;   // cube row
   } else {
     block_segment(a, DUMP, dl, seg);
   }
@@ -390,7 +421,7 @@ __global__ __launch_bounds__(kBlock) void fringe_kernel(FringeArgs a) {
   const int l = a.win_len[wi];
   const int q = seg - a.win_off[wi];
   const int64_t k0 = a.win_k0[wi] + int64_t(q) * a.win_hop[wi];
-  const float2 *wd = a.w + int64_t(dl) * a.w_dm_stride + k0 * NJ;
+  const float2 *wd = LIST ? nullptr : a.w + int64_t(dl) * a.w_dm_stride + k0 * NJ;
   const float2 *rph = a.rate_ph + a.rate_off[wi];
 
   int x_off, s_off, t_off, total;
@@ -441,7 +472,10 @@ __global__ __launch_bounds__(kBlock) void fringe_kernel(FringeArgs a) {
 
   for (int r = 0; r < R; ++r) {
     float2 y[JA];
-    segment_sum<JA, JB>(y, wd, rph, r, N, J, l, R, s_p1, n1, i2s);
+    if constexpr (LIST)
+      segment_sum_direct<JA, JB>(y, a, lb, ld, k0, rph, r, N, J, l, R, s_p1, n1, i2s);
+    else
+      segment_sum<JA, JB>(y, wd, rph, r, N, J, l, R, s_p1, n1, i2s);
 
     for (int c = 0; c < P; ++c) {
       __syncthreads();
