@@ -12,7 +12,10 @@
 //                      in-register passes with an LDS transpose), then the
 //                      M-point MBD transform over the IF lattice for each SBD
 //                      column (two in-register passes, wave-local LDS
-//                      transpose) and keeps the peak of |G|^2.  VALU-bound.
+//                      transpose; one pass for compact IF lattices) and
+//                      keeps the peak of |G|^2.  VALU-bound.  List launches
+//                      search selected segments, gathering their sums from
+//                      the input (re-evaluation near the threshold).
 //   fringe_mfma_kernel the same search with the MBD transform as a
 //                      real-embedded complex GEMM on the matrix cores (float16
 //                      operands, float32 accumulation; one product, or three
