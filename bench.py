@@ -259,7 +259,8 @@ def run_form(args, wl, V, prec, dev, truth=None):
     from paper_1801_02391_amd import frbx
     from paper_1801_02391_amd import workloads as W
     lay = wl["layout"]
-    # "f16-recheck": the f16 form with near-threshold segments re-evaluated in f32
+    # "f16-recheck": the f16 form with every segment above threshold - band
+    # (the crossings and the segments near the threshold) re-evaluated in f32
     base_prec = "f16" if prec == "f16-recheck" else prec
     band = args.recheck_band if prec == "f16-recheck" else 0.0
     srch = dict(wl["search"], precision=base_prec, recheck_band=band)
@@ -367,8 +368,8 @@ def run_form(args, wl, V, prec, dev, truth=None):
         "vs_baseline": None,
         "dtype": {"f32": "f32", "f16x3": "f16x3 (MBD: 3 f16 MFMA products, f32 accumulate)",
                   "f16": "f16 storage + f16 MFMA, f32 accumulate",
-                  "f16-recheck": f"f16 storage + f16 MFMA, f32 accumulate; segments within "
-                                 f"{band} of the threshold re-evaluated in f32"}[prec],
+                  "f16-recheck": f"f16 storage + f16 MFMA, f32 accumulate; segments above "
+                                 f"threshold - {band} re-evaluated in f32"}[prec],
         "data": "synthetic",
         "config": {"workload": args.workload, "baselines": B, "if": N, "chan": J,
                    "frames": lay["n_frames"], "dm_trials": D, "rate_bins": R, "sbd_bins": PJ,
@@ -578,8 +579,8 @@ def main():
                          "of its baselines (default 1), --chunks 1 s chunks, the last two timed")
     ap.add_argument("--chunks", type=int, default=6)
     ap.add_argument("--recheck-band", type=float, default=0.05,
-                    help="band around the threshold (in normalised power) re-evaluated in f32 "
-                         "by the f16-recheck form")
+                    help="the f16-recheck form re-evaluates in f32 every segment whose "
+                         "normalised power exceeds threshold - band")
     ap.add_argument("--quant-error", action="store_true",
                     help="with --stream: search the chunks again unquantised and report the "
                          "FP8 storage error in the data, the powers and the detections")

@@ -175,14 +175,14 @@ typedef enum { FRBX_PREC_F32 = 0, FRBX_PREC_F16X3 = 1, FRBX_PREC_F16 = 2 } frbx_
 
 frbx_status frbx_set_precision(frbx_ctx *ctx, int32_t precision);
 
-/* Near-threshold re-evaluation for the matrix-core forms (not a step of the
- * paper; it gives their threshold decisions float32 arithmetic).  With
- * band > 0, after the search in FRBX_PREC_F16X3 or FRBX_PREC_F16 (frbx_run
- * or frbx_stream_push), every segment whose Eq. 6 normalised power lies
- * within `band` of the threshold is searched again by the float32 kernel
- * (its segment sums gathered straight from the input with the AP offsets),
- * its power and index are replaced in the cube, and the statistics,
- * crossings and detections are taken from the updated cube.  band = 0 (default) turns it off; ignored in
+/* Float32 re-evaluation of the crossings of the matrix-core forms (not a
+ * step of the paper; it gives their threshold decisions and crossing peaks
+ * float32 arithmetic).  With band > 0, after the search in FRBX_PREC_F16X3
+ * or FRBX_PREC_F16 (frbx_run or frbx_stream_push), every segment whose
+ * Eq. 6 normalised power exceeds threshold - band is searched again by the
+ * float32 kernel (its segment sums gathered straight from the input with
+ * the AP offsets), its power and index are replaced in the cube, and the
+ * statistics, crossings and detections are taken from the updated cube.  band = 0 (default) turns it off; ignored in
  * FRBX_PREC_F32; FRBX_E_INVAL for band < 0, and at frbx_run for a shape the
  * float32 search does not support. */
 frbx_status frbx_set_recheck(frbx_ctx *ctx, double band);

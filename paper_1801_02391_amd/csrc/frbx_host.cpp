@@ -950,11 +950,12 @@ frbx_status stats_pass(frbx_ctx *c, frbx::StatsArgs &st, size_t rows, int64_t S,
   return FRBX_OK;
 }
 
-// Re-evaluation of near-threshold segments after a matrix-core pass: the
-// segments with |P_norm - threshold| < band (normalised with this pass's
-// statistics) are searched again by the float32 kernel in one launch (one
-// work-group per segment, the segment sums gathered straight from the
-// input); their powers and indices in the cube are replaced.
+// Re-evaluation after a matrix-core pass: the segments whose normalised
+// power (with this pass's statistics) exceeds threshold - band, i.e. every
+// crossing and every segment near the threshold, are searched again by the
+// float32 kernel in one launch (one work-group per segment, the segment
+// sums gathered straight from the input); their powers and indices in the
+// cube are replaced, so the crossings carry float32 peaks and cells.
 frbx_status recheck_pass(frbx_ctx *c, const PassSpec &ps, frbx::StatsArgs &st, size_t rows) {
   frbx_status s;
   const int D = c->n_dm, NJ = c->N * c->J, nw = int(c->windows.size()), J = c->J, M = c->n_mbd;
@@ -965,7 +966,6 @@ frbx_status recheck_pass(frbx_ctx *c, const PassSpec &ps, frbx::StatsArgs &st, s
   if ((s = stats_pass(c, st, rows, S, c->threshold - c->recheck_band, near)) != FRBX_OK) return s;
   std::vector<int32_t> list;
   for (const DevCrossing &x : near) {
-    if (!(x.pnorm < c->threshold + c->recheck_band)) continue;
     const int bd = x.row / nw;
     list.push_back(bd / D);
     list.push_back(bd % D);

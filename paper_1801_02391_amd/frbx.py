@@ -311,7 +311,8 @@ class Search:
         return dict(dk_max=dkm.value, hop=hop.tolist(), n_seg=nseg.tolist(), total=tot.value)
 
     def recheck(self):
-        """(band, segments re-evaluated in float32 by the last run or push)."""
+        """(band, segments re-evaluated in float32 by the last run or push: those
+        whose normalised power exceeded threshold - band)."""
         band = C.c_double(0.0)
         n = C.c_int64(0)
         self._chk(lib().frbx_get_recheck(self._h, C.byref(band), C.byref(n)), "get_recheck")

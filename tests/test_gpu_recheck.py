@@ -1,11 +1,13 @@
-"""GPU tests of the near-threshold re-evaluation of the matrix-core forms:
-segments whose normalised power lies within a band of the threshold are
-searched again by the float32 kernel (one work-group per listed segment).
+"""GPU tests of the float32 re-evaluation of the matrix-core forms: the
+segments whose normalised power exceeds threshold - band (every crossing and
+the segments near the threshold) are searched again by the float32 kernel
+(one work-group per listed segment).
 With a band that takes every segment, the cube must equal the float32
 search's (to float32 rounding: the list kernel gathers the segment sums from
 the input instead of a dedispersed copy, so the compiler may round a complex
 product in another order); with a narrow band, the re-evaluated segments
-carry float32 powers and the threshold decisions follow float32 arithmetic."""
+carry float32 powers and cells, so the crossings and detections follow
+float32 arithmetic."""
 import numpy as np
 import pytest
 import torch
@@ -70,7 +72,7 @@ def test_band_over_every_segment_reproduces_float32(prec, N):
     assert _det(s.candidates()) == _det(s32.candidates())
 
 
-def test_near_threshold_band_takes_float32_decisions():
+def test_narrow_band_takes_float32_crossings_and_detections():
     N = 9
     V, _ = W.generate(_wl(N))
     s32, P32, I32 = _run(_wl(N, precision="f32"), V)
@@ -83,11 +85,19 @@ def test_near_threshold_band_takes_float32_decisions():
     # the re-evaluated segments hold the float32 search's values
     assert _close(P[changed], P32[changed])
     assert np.mean(I[changed] == I32[changed]) > 0.99
+    # every crossing was re-evaluated: f32 values and cells
+    cr = s.crossings()
+    assert len(cr) <= n
+    seg_vals = {_key(c): (c["power"], c["rate_idx"], c["sbd_idx"], c["mbd_idx"]) for c in s32.crossings()}
+    common = [c for c in cr if _key(c) in seg_vals]
+    assert all(abs(c["power"] - seg_vals[_key(c)][0]) <= REL * seg_vals[_key(c)][0] for c in common)
+    assert np.mean([(c["rate_idx"], c["sbd_idx"], c["mbd_idx"]) == seg_vals[_key(c)][1:] for c in common]) > 0.99
     # crossings: as float32 except for ones within 1e-3 of the threshold
-    a = {_key(c): c["power_norm"] for c in s.crossings()}
+    a = {_key(c): c["power_norm"] for c in cr}
     b = {_key(c): c["power_norm"] for c in s32.crossings()}
     for k in set(a) ^ set(b):
         assert abs(a.get(k, b.get(k)) - 3.0) <= 1e-3
+    assert _det(s.candidates()) == _det(s32.candidates())
     note(f"rechecked {n}; f16 crossings differing from f32 without recheck: "
          f"{len(set(a) ^ set(_key(c) for c in s16.crossings()))}")
 
