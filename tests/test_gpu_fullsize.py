@@ -3,7 +3,8 @@
 cells) searched exactly as bench.py times it, checked on sampled outputs
 that the FP64 oracle computes segment by segment: powers and peak indices
 of sampled cube entries (random ones and the strongest crossings) in all
-three forms, the Eq. 6 statistics against the device's own cube, and the
+three forms, the Eq. 6 statistics against the device's own cube, the f16
+form with float32 re-evaluation against the f32 detections, and the
 refinement of the top 1024 peaks against the oracle's gradient and central
 differences."""
 import numpy as np
@@ -29,13 +30,19 @@ def vgos():
     return wl, V
 
 
-def _run(wl, V, prec):
+def _run(wl, V, prec, band=0.0):
     s = frbx.Search(wl["layout"])
-    s.configure(dict(wl["search"], precision=prec))
+    s.configure(dict(wl["search"], precision=prec, recheck_band=band))
     s.load(torch.from_numpy(W.to_complex32(V) if prec == "f16" else V).cuda())
-    note(f"full search, {prec}")
+    note(f"full search, {prec}, recheck band {band}")
     s.run()
     return s
+
+
+@pytest.fixture(scope="module")
+def f32_search(vgos):
+    wl, V = vgos
+    return _run(wl, V, "f32")
 
 
 def _samples(s, wl, n_random=40, n_top=16, seed=3):
@@ -76,9 +83,9 @@ def _check(P, I, off, ora, rtol, margin):
     return worst, n_idx
 
 
-def test_full_size_f32_sampled_against_the_oracle(vgos):
+def test_full_size_f32_sampled_against_the_oracle(vgos, f32_search):
     wl, V = vgos
-    s = _run(wl, V, "f32")
+    s = f32_search
     entries, off = _samples(s, wl)
     ora = _oracle_entries(wl, V, entries)
     P, I = s.power_cube()
@@ -110,9 +117,30 @@ def test_full_size_matrix_core_forms_sampled(vgos, prec):
     note(f"{prec}: {len(entries)} sampled segments, worst power rel err {worst:.2e}, {n_idx} index checks")
 
 
-def test_full_size_refinement_of_the_top_1024_peaks(vgos):
+def test_full_size_f16_with_recheck_detects_as_float32(vgos, f32_search):
+    """f16 with every segment above threshold - 0.05 re-evaluated in f32:
+    the detections equal the f32 search's, and every crossing that differs
+    lies within 1e-3 x threshold of it."""
     wl, V = vgos
-    s = _run(wl, V, "f32")
+    s = _run(wl, V, "f16", band=0.05)
+    band, n = s.recheck()
+    note(f"f16 + recheck: {n} segments re-evaluated")
+    assert band == 0.05 and n > 0
+
+    def det(cands):
+        return [(c["baseline"], c["dm_index"], c["window_len"], c["k0"]) for c in cands]
+    assert det(s.candidates()) == det(f32_search.candidates())
+    thr = wl["search"]["threshold"]
+    key = lambda c: (c["baseline"], c["dm_index"], c["window_index"], c["segment"])
+    a = {key(c): c["power_norm"] for c in s.crossings()}
+    b = {key(c): c["power_norm"] for c in f32_search.crossings()}
+    for k in set(a) ^ set(b):
+        assert abs(a.get(k, b.get(k)) - thr) <= 1e-3 * thr
+
+
+def test_full_size_refinement_of_the_top_1024_peaks(vgos, f32_search):
+    wl, V = vgos
+    s = f32_search
     peaks = s.top_peaks(1024)
     assert len(peaks) == 1024
     th0 = s.refine_begin(peaks)
