@@ -21,8 +21,11 @@
  *   One context belongs to one host thread and one HIP stream.
  *   Device memory is allocated only by the entry points that size a
  *   workspace (frbx_load*, frbx_run, frbx_stream_begin/push, frbx_power_sum,
- *   frbx_refine_begin, frbx_dump_segment); it is reused across calls and
- *   freed by frbx_destroy.  No entry point frees memory the caller owns.
+ *   frbx_refine_begin, frbx_dump_segment, frbx_calibrate) and by those that
+ *   build the grid tables on the device after a grid changed
+ *   (frbx_get_segments, frbx_get_lattice, frbx_get_ap_offsets,
+ *   frbx_refine_cells); it is reused across calls and freed by
+ *   frbx_destroy.  No entry point frees memory the caller owns.
  */
 #ifndef FRBX_H
 #define FRBX_H
