@@ -51,7 +51,12 @@ typedef enum {
  * with sky frequency if_freq_mhz[n] (lower edge, upper sideband), frequency
  * point j in [0, J) at baseband frequency j * chan_bw_mhz, accumulation
  * period (AP) k in [0, K) of t_ap_ms.  The pointer is read during
- * frbx_create only. */
+ * frbx_create only.  One work-group searches one segment, one lane per
+ * (IF, channel group): N may be at most 128, 64, 64, 32, 32, 16 for J = 8,
+ * 16, 32, 64, 128, 256, and the segment's LDS plan (which grows with N, J,
+ * sbd_pad and n_mbd) must fit 150 KiB; a larger shape is refused with
+ * FRBX_E_INVAL when the grids are first used (frbx_run, frbx_get_segments,
+ * ...). */
 typedef struct {
   int32_t n_baselines;        /* B >= 1                          */
   int32_t n_if;               /* N >= 1                          */
