@@ -58,12 +58,20 @@ int main(int argc, char **argv) {
   if (check(frbx_get_power_cube(c, p, idx, n, &n), c, "power cube")) return 6;
   int64_t nc = 0;
   frbx_get_candidates(c, NULL, 0, &nc);
+  int64_t *q = malloc(sizeof(int64_t) * (size_t)N);
+  double mbd_step = 0.0;
+  int32_t shift = 0;
+  if (check(frbx_get_lattice(c, q, &mbd_step, &shift), c, "lattice")) return 8;
   FILE *fo = fopen(argv[2], "wb");
   if (!fo) return 7;
   fwrite(p, sizeof(float), (size_t)n, fo);
   fwrite(idx, sizeof(int32_t), (size_t)n, fo);
   fclose(fo);
   printf("cube %lld candidates %lld\n", (long long)n, (long long)nc);
+  printf("lattice %d %.17g", (int)shift, mbd_step);
+  for (int i = 0; i < N; ++i) printf(" %lld", (long long)q[i]);
+  printf("\n");
+  free(q);
   frbx_destroy(c);
   free(p);
   free(idx);

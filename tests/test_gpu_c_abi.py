@@ -47,3 +47,8 @@ def test_search_from_c_equals_the_binding(tmp_path):
     P, I = s.power_cube()
     assert np.array_equal(P.ravel().view(np.uint32), Pc.view(np.uint32)) and np.array_equal(I.ravel(), Ic)
     assert int(r.stdout.split()[3]) == len(s.candidates())
+    # the MBD lattice seen from C equals the binding's
+    lat = s.lattice()
+    line = r.stdout.splitlines()[1].split()
+    assert line[0] == "lattice" and int(line[1]) == lat["compact_shift"]
+    assert float(line[2]) == lat["mbd_step_us"] and [int(x) for x in line[3:]] == lat["q"]
