@@ -519,6 +519,8 @@ __global__ __launch_bounds__(kBlock) void fringe_kernel(FringeArgs a) {
         }
       } else {
         // MBD over the IF lattice, one column a of this SBD tile per group.
+        // Unrolled by 4: the columns' LDS offsets become immediates.
+#pragma unroll 4
         for (int a0 = 0; a0 < J; a0 += COLS) {
           const int col = a0 + grp;
           if (col < J) {
