@@ -48,3 +48,18 @@ def test_short_stream_workload_generates_one_baseline():
     V, truth = W.generate(wl, baselines=[0])
     assert V.shape == (1, 16, 256, 40000) and V.dtype == np.complex64
     assert len(truth["pulses"]) == 3
+
+
+def test_algorithmic_flops_per_cell_of_the_roofline():
+    """FFT-form work per cell behind the f32 roofline, against the count
+    written out by hand: per (segment, rate) N 5 PJ log2 PJ (SBD) +
+    PJ 5 M log2 M (MBD) + 4 PJ M (|G|^2 and compare) + 8 N J (rotated
+    segment sum), over PJ M cells."""
+    sys.path.insert(0, ROOT)
+    import bench
+    # VGOS: N = 32, J = 64, PJ = 256, M = 256:
+    # (327680 + 2621440 + 262144 + 16384) / 65536
+    assert bench.fringe_flops_per_cell(32, 64, 4, 256) == 3227648 / 65536 == 49.25
+    # streaming: N = 16, J = 256, PJ = 1024, M = 256:
+    # (819200 + 10485760 + 1048576 + 32768) / 262144
+    assert bench.fringe_flops_per_cell(16, 256, 4, 256) == 12386304 / 262144 == 47.25
