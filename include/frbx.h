@@ -240,6 +240,13 @@ frbx_status frbx_get_segments(const frbx_ctx *ctx, int64_t *dk_max, int32_t *hop
 frbx_status frbx_get_lattice(const frbx_ctx *ctx, int64_t *q, double *mbd_step_us,
                              int32_t *compact_shift);
 
+/* The same lattice for a layout without a context (host only, no device):
+ * n_mbd in {16, 32, 64, 128, 256}, mbd_step_us <= 0 for T/M; FRBX_E_INVAL
+ * for a layout or grid that frbx_set_delay_grid / frbx_run would refuse
+ * (offsets not on the lattice, two IFs on one point). */
+frbx_status frbx_mbd_lattice(const frbx_layout *layout, int32_t n_mbd, double mbd_step_us, int64_t *q,
+                             double *mbd_step_out, int32_t *compact_shift);
+
 /* AP offsets of Eq. 2 for the current DM grid: [D][N][J] int32 (host). */
 frbx_status frbx_get_ap_offsets(const frbx_ctx *ctx, int32_t *out, int64_t cap, int64_t *n);
 

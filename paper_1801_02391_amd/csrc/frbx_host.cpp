@@ -288,6 +288,67 @@ int64_t offset_gcd_khz(const std::vector<double> &f0) {
   return g;
 }
 
+// MBD lattice of Eq. 5 (grid of M points of step mbd_step over the
+// ambiguity t_amb): the lattice position q[n] of every IF, the IF on each
+// position (row[q], N if none), and the compact form of the float32 kernel:
+// a common shift of the positions that brings them all below the first
+// pass's row count (shift -1 when there is none).  Returns an error text,
+// or nullptr.
+struct MbdLattice {
+  double t_amb = 0, mbd_step = 0;
+  std::vector<int32_t> row;
+  std::vector<int64_t> q;
+  std::vector<int32_t> pos;
+  int32_t shift = -1;
+};
+
+const char *mbd_lattice(const std::vector<double> &f0, int J, double df, int M, double step_req,
+                        MbdLattice &L) {
+  const int N = int(f0.size());
+  const int64_t g = offset_gcd_khz(f0);
+  if (g > 0)
+    L.t_amb = 1000.0 / double(g);
+  else if (g == 0)
+    L.t_amb = 1.0 / (J * df);
+  else if (!(step_req > 0))
+    return "IF offsets are not whole kHz: give an explicit MBD step";
+  else
+    L.t_amb = step_req * M;
+  L.mbd_step = step_req > 0 ? step_req : L.t_amb / M;
+  L.row.assign(M, N);
+  for (int n = 0; n < N; ++n) {
+    const double x = (f0[n] - f0[0]) * L.mbd_step * M;
+    const double r = std::nearbyint(x);
+    if (std::fabs(x - r) > 1e-6) return "MBD step does not put every IF on the transform lattice";
+    int64_t qn = static_cast<int64_t>(r) % M;
+    if (qn < 0) qn += M;
+    if (L.row[qn] != N) return "two IFs fall on the same MBD lattice point: raise n_mbd";
+    L.row[qn] = n;
+  }
+  L.q.assign(N, 0);
+  for (int qq = 0; qq < M; ++qq)
+    if (L.row[qq] < N) L.q[L.row[qq]] = qq;
+  // Compact lattice: a common shift of the positions (a phase factor on G,
+  // |G| unchanged) that brings every IF below the row count of the first MBD
+  // pass lets the f32 kernel skip that pass.
+  L.pos.clear();
+  L.shift = -1;
+  const int compact_rows = frbx::fringe_compact_rows(M);
+  for (int n0 = 0; n0 < N && L.pos.empty(); ++n0) {
+    std::vector<int32_t> pos(N);
+    bool fits = true;
+    for (int n = 0; n < N; ++n) {
+      pos[n] = int32_t(((L.q[n] - L.q[n0]) % M + M) % M);
+      fits = fits && pos[n] < compact_rows;
+    }
+    if (fits) {
+      L.pos = pos;
+      L.shift = int32_t(L.q[n0]);
+    }
+  }
+  return nullptr;
+}
+
 // exp(-i 2 pi x) for x in cycles, reduced to [-1/2, 1/2) first
 float2 cis_cycles(double x) {
   const double r = x - std::nearbyint(x);
@@ -342,48 +403,15 @@ frbx_status prepare(frbx_ctx *c) {
   if (tot > (int64_t(1) << 30)) return c->fail(FRBX_E_INVAL, "too many segments per DM trial");
   // MBD lattice (Eq. 5 MBD term on a grid of M points)
   const int M = c->n_mbd;
-  const int64_t g = offset_gcd_khz(c->f0);
-  if (g > 0)
-    c->t_amb = 1000.0 / double(g);
-  else if (g == 0)
-    c->t_amb = 1.0 / (J * c->df);
-  else if (!(c->mbd_step_req > 0))
-    return c->fail(FRBX_E_INVAL, "IF offsets are not whole kHz: give an explicit MBD step");
-  else
-    c->t_amb = c->mbd_step_req * M;
-  c->mbd_step = c->mbd_step_req > 0 ? c->mbd_step_req : c->t_amb / M;
-  c->mbd_row.assign(M, N);
-  for (int n = 0; n < N; ++n) {
-    const double x = (c->f0[n] - c->f0[0]) * c->mbd_step * M;
-    const double r = std::nearbyint(x);
-    if (std::fabs(x - r) > 1e-6)
-      return c->fail(FRBX_E_INVAL, "MBD step does not put every IF on the transform lattice");
-    int64_t qn = static_cast<int64_t>(r) % M;
-    if (qn < 0) qn += M;
-    if (c->mbd_row[qn] != N)
-      return c->fail(FRBX_E_INVAL, "two IFs fall on the same MBD lattice point: raise n_mbd");
-    c->mbd_row[qn] = n;
-  }
-  c->q_if.assign(N, 0);
-  for (int qq = 0; qq < M; ++qq)
-    if (c->mbd_row[qq] < N) c->q_if[c->mbd_row[qq]] = qq;
-  // Compact lattice: a common shift of the positions (a phase factor on G,
-  // |G| unchanged) that brings every IF below the row count of the first MBD
-  // pass lets the f32 kernel skip that pass.
-  c->mbd_pos.clear();
-  c->mbd_shift = -1;
-  const int compact_rows = frbx::fringe_compact_rows(M);
-  for (int n0 = 0; n0 < N && c->mbd_pos.empty(); ++n0) {
-    std::vector<int32_t> pos(N);
-    bool fits = true;
-    for (int n = 0; n < N; ++n) {
-      pos[n] = int32_t(((c->q_if[n] - c->q_if[n0]) % M + M) % M);
-      fits = fits && pos[n] < compact_rows;
-    }
-    if (fits) {
-      c->mbd_pos = pos;
-      c->mbd_shift = int32_t(c->q_if[n0]);
-    }
+  {
+    MbdLattice L;
+    if (const char *why = mbd_lattice(c->f0, J, c->df, M, c->mbd_step_req, L)) return c->fail(FRBX_E_INVAL, why);
+    c->t_amb = L.t_amb;
+    c->mbd_step = L.mbd_step;
+    c->mbd_row = L.row;
+    c->q_if = L.q;
+    c->mbd_pos = L.pos;
+    c->mbd_shift = L.shift;
   }
   // rate grid (Eq. 4)
   int lmax = 1;
@@ -1939,6 +1967,20 @@ frbx_status frbx_ap_offsets(const frbx_layout *L, double dm_lo, double dm_step, 
     return FRBX_E_INVAL;
   ap_offset_table(L->n_if, L->n_chan, L->if_freq_mhz, L->chan_bw_mhz, L->t_ap_ms, dm_lo, dm_step, n_dm,
                   k_dm > 0 ? k_dm : kDefaultKdm, out);
+  return FRBX_OK;
+}
+
+frbx_status frbx_mbd_lattice(const frbx_layout *Lay, int32_t n_mbd, double mbd_step_us, int64_t *q,
+                             double *mbd_step_out, int32_t *compact_shift) {
+  std::string why;
+  if (check_layout(Lay, why) != FRBX_OK || frbx::fringe_compact_rows(n_mbd) == 0) return FRBX_E_INVAL;
+  std::vector<double> f0(Lay->if_freq_mhz, Lay->if_freq_mhz + Lay->n_if);
+  MbdLattice L;
+  if (mbd_lattice(f0, Lay->n_chan, Lay->chan_bw_mhz, n_mbd, mbd_step_us, L)) return FRBX_E_INVAL;
+  if (q)
+    for (int n = 0; n < Lay->n_if; ++n) q[n] = L.q[n];
+  if (mbd_step_out) *mbd_step_out = L.mbd_step;
+  if (compact_shift) *compact_shift = L.shift;
   return FRBX_OK;
 }
 

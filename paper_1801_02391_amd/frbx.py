@@ -101,6 +101,7 @@ _SIGS = {
     "frbx_power_sum": ([_P, _P, C.c_int32, _P, C.c_int64, _P], C.c_int),
     "frbx_calibrate": ([_P, C.c_int32, C.c_int64, C.c_int32, _P, _P], C.c_int),
     "frbx_get_timing": ([_P, _P], C.c_int),
+    "frbx_mbd_lattice": ([C.POINTER(Layout), C.c_int32, C.c_double, _P, _P, _P], C.c_int),
     "frbx_ap_offsets": ([C.POINTER(Layout), C.c_double, C.c_double, C.c_int32, C.c_double, _P],
                         C.c_int),
     "frbx_detect": ([_P, C.c_int64, C.c_double, C.c_int32, C.c_int32, C.c_int32, _P, C.c_int64,
@@ -168,6 +169,21 @@ def ap_offsets(layout, dm_lo, dm_step, n_dm, k_dm=0.0):
     if s != OK:
         raise FrbxError(s, "frbx_ap_offsets")
     return out
+
+
+def mbd_lattice(layout, n_mbd, mbd_step_us=0.0):
+    """Host-only MBD lattice of a layout (no device needed): the IFs' lattice
+    positions, the MBD step (us) and the shift of the compact one-pass form
+    of the float32 transform (-1: two-pass form)."""
+    st, f0 = _layout_struct(layout)
+    q = np.zeros(len(f0), dtype=np.int64)
+    step = C.c_double(0.0)
+    shift = C.c_int32(0)
+    s = lib().frbx_mbd_lattice(C.byref(st), int(n_mbd), float(mbd_step_us), _ptr(q), C.byref(step),
+                               C.byref(shift))
+    if s != OK:
+        raise FrbxError(s, "frbx_mbd_lattice")
+    return dict(q=q.tolist(), mbd_step_us=step.value, compact_shift=shift.value)
 
 
 def detect(crossings, t_amb_us, n_win_min, n_bl_min, use_mbd=True):

@@ -156,3 +156,55 @@ def test_detect_capacity_protocol():
     nd, ng = C.c_int64(-1), C.c_int64(-1)
     s = L.frbx_detect(arr, 2, 1.0, 1, 2, 1, None, 0, C.byref(nd), None, 0, C.byref(ng))
     assert s == frbx.E_RANGE and nd.value == 2 and ng.value == 1
+
+
+def _lattice_rule(f0, n_mbd, t_amb):
+    """Independent statement of the lattice and of the compact-form rule:
+    q_n = (f_n - f_0) T mod M; the one-pass form applies when a shift by one
+    IF's position brings every position below the first pass's row count
+    (4, 4, 8, 8, 16 rows for M = 16 ... 256), the first such IF (in IF
+    order) giving the shift."""
+    q = [int(round((f - f0[0]) * t_amb)) % n_mbd for f in f0]
+    rows = {16: 4, 32: 4, 64: 8, 128: 8, 256: 16}[n_mbd]
+    shift = next((s for s in q if max((x - s) % n_mbd for x in q) < rows), -1)
+    return q, shift
+
+
+@pytest.mark.parametrize("name", W.workload_names())
+def test_mbd_lattice_of_the_workloads(name):
+    wl = W.get_workload(name)
+    lay, srch = wl["layout"], wl["search"]
+    t_amb = O.build_grids(lay, srch)["t_amb"]
+    got = frbx.mbd_lattice(lay, srch["n_mbd"])
+    q, shift = _lattice_rule(lay["if_freq_mhz"], srch["n_mbd"], t_amb)
+    assert got["q"] == q and got["compact_shift"] == shift
+    assert got["mbd_step_us"] == pytest.approx(t_amb / srch["n_mbd"], rel=1e-12)
+
+
+def test_mbd_lattice_random_sets_and_edges():
+    rng = np.random.default_rng(11)
+    for trial in range(200):
+        M = int(rng.choice([16, 32, 64, 128, 256]))
+        span = int(rng.choice([4, 8, 16, 17, M]))
+        N = int(rng.integers(1, min(M, 12, 2 * span) + 1))
+        pts = rng.choice(np.arange(-span, span), size=N, replace=False)
+        pts = pts - pts[0]                        # IF 0 at offset 0
+        if len(set(int(p) % M for p in pts)) < N:
+            continue
+        f0 = [8000.0 + 16.0 * int(p) for p in pts]   # offsets >= -2M x 16 MHz stay positive
+        lay = dict(n_baselines=1, if_freq_mhz=f0, n_chan=16, chan_bw_mhz=1.0, t_ap_ms=1.0, n_frames=64)
+        got = frbx.mbd_lattice(lay, M)
+        nz = [int(p) for p in pts if p != 0]
+        g_mhz = float(np.gcd.reduce(np.abs(nz))) * 16.0 if nz else None
+        t_amb = 1.0 / g_mhz if g_mhz else 1.0 / (16 * 1.0)
+        q, shift = _lattice_rule(f0, M, t_amb)
+        assert got["q"] == q and got["compact_shift"] == shift, (M, f0)
+    # refused: two IFs on one lattice point (offsets 0 and 16 x 16 MHz at M = 16),
+    # and an unsupported number of MBD points
+    lay = dict(n_baselines=1, if_freq_mhz=[3000.0, 3016.0, 3256.0], n_chan=16, chan_bw_mhz=1.0,
+               t_ap_ms=1.0, n_frames=64)
+    with pytest.raises(frbx.FrbxError):
+        frbx.mbd_lattice(lay, 16)
+    assert frbx.mbd_lattice(lay, 32)["compact_shift"] == -1     # q = 0, 1, 16: span 16 > 4 rows
+    with pytest.raises(frbx.FrbxError):
+        frbx.mbd_lattice(lay, 100)
