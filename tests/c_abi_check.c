@@ -25,6 +25,14 @@ int main(void) {
   printf("dk");
   for (int i = 0; i < 3 * 4 * 16; ++i) printf(" %d", tab[i]);
   printf("\n");
+  /* MBD lattice: offsets 0, 32, 96, 192 MHz on a 32 MHz lattice */
+  int64_t q[4];
+  double mbd_step = 0.0;
+  int32_t shift = 0;
+  if (frbx_mbd_lattice(&lay, 256, 0.0, q, &mbd_step, &shift) != FRBX_OK) return 1;
+  printf("lattice %d %.17g %lld %lld %lld %lld\n", (int)shift, mbd_step, (long long)q[0], (long long)q[1],
+         (long long)q[2], (long long)q[3]);
+  if (frbx_mbd_lattice(&lay, 100, 0.0, q, &mbd_step, &shift) != FRBX_E_INVAL) return 1;
   /* two baselines crossing at overlapping APs -> one reported group */
   frbx_candidate cr[3];
   memset(cr, 0, sizeof cr);

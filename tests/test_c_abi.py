@@ -28,6 +28,9 @@ def test_c_program_uses_the_abi(tmp_path):
     dk = np.array(list(map(int, lines["dk"]))).reshape(3, 4, 16)
     ora = O.ap_offsets(O.dm_trials(0.0, 150.0, 3), [3000.0, 3032.0, 3096.0, 3192.0], 16, 1.0, 1.0, 4.149e6)
     assert np.array_equal(dk, ora)
+    # positions 0, 1, 3, 6 of a 32 MHz lattice (T = 1/32 us): the one-pass form, shift 0
+    assert lines["lattice"][0] == "0" and float(lines["lattice"][1]) == 1.0 / 32 / 256
+    assert lines["lattice"][2:] == ["0", "1", "3", "6"]
     # baseline 0 has two overlapping windows -> one detection (the 8-AP window
     # is inserted first, the higher normalised power survives); baseline 1 one;
     # they overlap in time -> one group of 2 baselines, reported
