@@ -592,8 +592,8 @@ def main():
                          "multiply by 1) of this many MiB, to calibrate HBM counters")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU only: --gpus must be 1 "
-                                   "(the sharding design is described in DESIGN.md)"}))
+        print(json.dumps({"error": "frbx searches on one GPU only: --gpus must be 1 (across "
+                                   "GPUs the search would be split by baseline, which is not built)"}))
         sys.exit(2)
 
     import numpy as np
