@@ -190,9 +190,10 @@ frbx_status frbx_set_precision(frbx_ctx *ctx, int32_t precision);
  * Eq. 6 normalised power exceeds threshold - band is searched again by the
  * float32 kernel (its segment sums gathered straight from the input with
  * the AP offsets), its power and index are replaced in the cube, and the
- * statistics, crossings and detections are taken from the updated cube.  band = 0 (default) turns it off; ignored in
- * FRBX_PREC_F32; FRBX_E_INVAL for band < 0, and at frbx_run for a shape the
- * float32 search does not support. */
+ * statistics, crossings and detections are taken from the updated cube.
+ * band = 0 (default) turns it off; ignored in FRBX_PREC_F32; FRBX_E_INVAL
+ * for band < 0.  Its launch is not among the kernel times of
+ * frbx_get_timing (the run's wall time includes it). */
 frbx_status frbx_set_recheck(frbx_ctx *ctx, double band);
 
 /* The current band and the number of segments re-evaluated by the last
