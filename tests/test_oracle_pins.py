@@ -261,6 +261,48 @@ def test_on_grid_rate_peaks_at_its_bin():
     assert np.all(np.delete(A, r_star) < 0.99 * A[r_star])
 
 
+def test_default_rate_step_hand_values():
+    """The rate-grid default (a convention; the paper drops the rate term of
+    Eq. 4): 1 / (2 f_max l_max t_ap) in Hz and seconds, f_max the highest
+    channel sky frequency.  Values worked by hand:
+      3000 MHz + 31 x 1 MHz points = 3.031e9 Hz, l_max 8, t_ap 1 ms:
+        1 / (2 x 3.031e9 x 8 x 1e-3) = 1 / 48 496 000 s/s;
+      VGOS top 10200 + 7 x 32 + 63 x 0.5 = 10455.5 MHz, l_max 16, 0.5 ms:
+        1 / (2 x 10455.5e6 x 16 x 5e-4) = 1 / 167 288 000 s/s."""
+    f0 = [3000.0 + 32 * n for n in range(1)]
+    step = O.default_rate_step(f0, 32, 1.0, 1.0, [2, 8, 4])
+    assert step == pytest.approx(1.0 / 48_496_000.0, rel=1e-14)
+    f0 = [b + 32 * i for b in (3000.0, 5240.0, 6360.0, 10200.0) for i in range(8)]
+    step = O.default_rate_step(f0, 64, 0.5, 0.5, [2, 4, 8, 16])
+    assert step == pytest.approx(1.0 / 167_288_000.0, rel=1e-14)
+
+
+@pytest.mark.parametrize("f0,J,df,t_ap,windows", [
+    ([3000.0 + 32 * n for n in range(8)], 32, 1.0, 1.0, [1, 2, 4, 8]),
+    ([2192.0 + 16 * n for n in range(6)], 32, 0.5, 1.024, [4, 8, 16, 24, 32]),
+    ([2000.0 + 768 * n for n in range(16)], 256, 0.125, 0.1, [10, 20, 40]),
+])
+def test_default_rate_step_is_half_a_cycle_over_the_longest_window(f0, J, df, t_ap, windows):
+    """The definition of the default rate step, checked physically: a delay
+    rate rho turns the fringe of sky frequency f by f rho seconds of phase
+    per second (a delay tau = rho t), so over the longest window (l_max APs
+    of t_ap) at the top channel frequency one step turns it by exactly half a
+    cycle; the grid built for a search uses that step, and the Eq. 4 rate
+    phasor at the top frequency advances by the same half cycle across
+    l_max APs."""
+    step = O.default_rate_step(f0, J, df, t_ap, windows)
+    f_top_hz = (max(f0) + (J - 1) * df) * 1e6       # MHz -> Hz
+    window_s = max(windows) * t_ap * 1e-3           # ms -> s
+    assert f_top_hz * step * window_s == pytest.approx(0.5, rel=1e-13)
+    lay = _layout(f0, J, df, t_ap, 4 * max(windows) + 10)
+    g = O.build_grids(lay, _search(n_mbd=256, n_rate=4, windows=windows))
+    assert g["rates"][3] - g["rates"][2] == pytest.approx(step, rel=1e-13)
+    assert g["rates"][2] == 0.0
+    ph = O.rate_phasor([step], [max(f0) + (J - 1) * df], max(windows), t_ap)[0, 0]
+    per_ap = -np.angle(ph[1] / ph[0]) / (2 * np.pi)  # cycles per AP (e^{-i phase})
+    assert per_ap * max(windows) == pytest.approx(0.5, rel=1e-12)
+
+
 # ---------------------------------------------------------------- P5 DM pulse
 def test_pulse_at_dm0_full_power_only_at_dm0():
     """Eqs. 1-3: a noise-free boxcar of w frames placed along the exact Eq. 2
