@@ -18,6 +18,8 @@ import os
 import sys
 import time
 
+T_START = time.perf_counter()   # the wall-clock budget counts from here
+
 ROOT = os.path.dirname(os.path.abspath(__file__))
 if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
@@ -66,30 +68,68 @@ def measured_traffic(key, workload):
     return float(vals[key])
 
 
-def mbd_form(s):
-    """Which form of the float32 MBD transform the search ran: the general
-    two-pass one, or the one-pass form of a compact IF lattice (which does
-    fewer operations than the FFT-form count behind `achieved`)."""
-    shift = s.lattice()["compact_shift"]
-    if shift < 0:
+def mbd_one_pass_rows(s, M):
+    """Rows of the one-pass MBD form when the float32 search runs it (compact
+    IF lattice), else 0 (the general two-pass form)."""
+    if s.lattice()["compact_shift"] < 0:
+        return 0
+    return {16: 4, 32: 4, 64: 8, 128: 8, 256: 16}[M]
+
+
+def mbd_form(rows):
+    if not rows:
         return {"mbd_form": "two-pass"}
-    return {"mbd_form": "one-pass (compact IF lattice)",
-            "note": "achieved counts the algorithmic FFT-form flops; the one-pass form skips "
-                    "the first MBD pass, so achieved can exceed the unpacked vector peak"}
+    return {"mbd_form": f"one-pass (compact IF lattice, {rows} rows)",
+            "note": "achieved counts the work of the one-pass form (the first MBD pass is skipped)"}
 
 
 def log(msg):
-    sys.stderr.write(f"[bench] {msg}\n")
+    sys.stderr.write(f"[bench {time.perf_counter() - T_START:6.1f} s] {msg}\n")
     sys.stderr.flush()
 
 
-def fringe_flops_per_cell(N, J, P, M):
+# A step longer than this gets one untimed warm-up only.
+LONG_STEP_S = 5.0
+# Planning guesses of a form's step time as a fraction of the f32 step on the
+# same workload (measured on MI355X; each form's own warm-up step replaces
+# the guess once it has run).
+FORM_COST = {"f32": 1.0, "f16x3": 0.9, "f16": 0.5, "f16-recheck": 0.55}
+# Time reserved for the refinement leg (library ascent, FP64 oracle
+# gradient check) and for loading a form's input onto the device.
+REFINE_RESERVE_S = 30.0
+LOAD_RESERVE_S = 8.0
+
+
+class Budget:
+    """Wall-clock budget of the whole run, counted from process start: the
+    timed steps of every form are sized so that the run prints its line
+    before the deadline (full steps only; the count actually timed is
+    reported)."""
+
+    def __init__(self, seconds):
+        self.deadline = T_START + seconds
+
+    def left(self):
+        return self.deadline - time.perf_counter()
+
+
+def fringe_flops_per_cell(N, J, P, M, one_pass_rows=0):
     """Algorithmic FP32 work per evaluated cell of the FFT-form search: per
     (segment, rate) an SBD transform per IF (N * 5 PJ log2 PJ), an MBD
     transform per SBD bin (PJ * 5 M log2 M), |G|^2 and compare (4 PJ M) and
-    the rotated segment sum (8 N J), divided by the PJ * M cells."""
+    the rotated segment sum (8 N J), divided by the PJ * M cells.
+
+    one_pass_rows = MB > 0 counts the one-pass MBD form of a compact IF
+    lattice instead, the work that form does: per SBD bin, M / MB lanes
+    each twiddle MB - 1 rows (6 flops each) and run one MB-point transform
+    (5 MB log2 MB)."""
     PJ = P * J
-    per = N * 5 * PJ * math.log2(PJ) + PJ * 5 * M * math.log2(M) + 4 * PJ * M + 8 * N * J
+    if one_pass_rows:
+        MB = one_pass_rows
+        mbd = PJ * (M // MB) * (6 * (MB - 1) + 5 * MB * math.log2(MB))
+    else:
+        mbd = PJ * 5 * M * math.log2(M)
+    per = N * 5 * PJ * math.log2(PJ) + mbd + 4 * PJ * M + 8 * N * J
     return per / (PJ * M)
 
 
@@ -165,12 +205,63 @@ def cpu_full(wl, V, gpu_candidates):
             "only_gpu": len(gpu - ora), **host_cpu()}
 
 
-def refine_leg(args, wl, s, truth):
+def oracle_fd_check(wl, V, cells, peaks, theta, g_dev, n_check, budget_s):
+    """The backward kernel's gradient against central differences of the
+    FP64 oracle's relaxed |G| (h = 1e-3 grid cell in every parameter) on
+    n_check peaks spread over the list.  Error of each component relative to
+    max(|fd|, 1e-2 P / cell); stops early when budget_s runs out."""
+    import numpy as np
+    from oracle import frb_oracle as O
+    lay, srch = wl["layout"], wl["search"]
+    N, J, K = lay["n_if"], lay["n_chan"], lay["n_frames"]
+    f0 = np.asarray(lay["if_freq_mhz"], dtype=np.float64)
+    kdm = srch.get("k_dm", O.K_DM_DEFAULT) or O.K_DM_DEFAULT
+    _, dxd = O.relaxed_offsets(1.0, f0, J, lay["chan_bw_mhz"], lay["t_ap_ms"], kdm)
+    cal = np.ones((N, J), complex)
+    errs, done = [], 0
+    t0 = time.perf_counter()
+    for i in np.unique(np.linspace(0, len(peaks) - 1, n_check).astype(int)):
+        if time.perf_counter() - t0 > budget_s:
+            break
+        p = peaks[i]
+        th = np.asarray(theta[i], dtype=np.float64)
+        l = p["window_len"]
+        # the frames the interpolation can touch, cast to float64 once
+        x_hi = (abs(th[3]) + cells[3]) * float(dxd.max())
+        lo = max(0, int(p["k0"]) - 16)
+        hi = min(K, int(p["k0"]) + l + int(math.ceil(x_hi)) + 16 + int(abs(th[4])))
+        Vb = np.asarray(V[p["baseline"], :, :, lo:hi], dtype=np.complex128)
+        k0 = int(p["k0"]) - lo
+
+        def P_of(t):
+            return abs(O.relaxed_fringe(Vb, lay, srch, cal, k0, l, t, kdm)[0])
+        P0 = P_of(th)
+        for k in range(5):
+            if cells[k] == 0:
+                continue
+            h = 1e-3 * cells[k]
+            e = np.zeros(5)
+            e[k] = h
+            fd = (P_of(th + e) - P_of(th - e)) / (2 * h)
+            errs.append(abs(g_dev[i, k] - fd) / max(abs(fd), 1e-2 * P0 / cells[k]))
+        done += 1
+    errs = np.asarray(errs)
+    if errs.size == 0:
+        return {"peaks_checked": 0}
+    return {"vs": "central differences of the FP64 oracle (h = 1e-3 cell), error relative to "
+                  "max(|fd|, 1e-2 P/cell)",
+            "peaks_checked": done, "components": int(errs.size),
+            "median": float(np.median(errs)), "p99": float(np.percentile(errs, 99)),
+            "max": float(errs.max()), "share_within_1e-3": float(np.mean(errs <= 1e-3)),
+            "seconds": round(time.perf_counter() - t0, 1)}
+
+
+def refine_leg(args, wl, V, s, truth, budget):
     """Refinement of the top coarse peaks (by normalised power) after the
     search: the library's ascent timed with HIP events, the gradient of the
-    backward kernel against central differences of the device forward, and
-    the distance of the refined parameters from the injected truth for the
-    peaks that belong to an injected pulse."""
+    backward kernel against central differences of the FP64 oracle, and the
+    distance of the refined parameters from the injected truth for the peaks
+    that belong to an injected pulse."""
     import numpy as np
     import torch
     lay, srch = wl["layout"], wl["search"]
@@ -186,27 +277,13 @@ def refine_leg(args, wl, s, truth):
     el = time.perf_counter() - t0
     tim = s.timing()
     cells, _ = s.refine_cells()
-    # gradient check on the device: central differences of the float32
-    # forward; steps of 1e-3 cell for the delays and rate, and steps that
-    # move the lowest channel by 0.01 AP for DM and the arrival offset (a DM
-    # cell can shift it by many APs); error relative to max(|fd|, 0.1 P/cell)
-    f0 = np.asarray(lay["if_freq_mhz"], dtype=np.float64)
-    f_lo, f_hi = f0.min(), f0.max() + (lay["n_chan"] - 1) * lay["chan_bw_mhz"]
-    kdm = srch.get("k_dm", 4.149e6) or 4.149e6
-    dx_max = kdm * (1.0 / f_lo ** 2 - 1.0 / f_hi ** 2) / lay["t_ap_ms"]
-    steps_h = [1e-3 * cells[0], 1e-3 * cells[1], 1e-3 * cells[2], 1e-2 / max(dx_max, 1e-12), 1e-2]
-    tt = torch.tensor(th0 + 0.25 * np.where(cells > 0, cells, 0.0), dtype=torch.float64, device="cuda")
+    # gradient check at a generic point a quarter cell off the grid
+    th_chk = th0 + 0.25 * np.where(cells > 0, cells, 0.0)
+    tt = torch.tensor(th_chk, dtype=torch.float64, device="cuda")
     g = s.refine_backward(tt, torch.ones(n, dtype=torch.float32, device="cuda")).cpu().numpy()
-    Pt = s.refine_forward(tt).cpu().numpy()
-    fd_err = []
-    for k in range(5):
-        if cells[k] == 0:
-            continue
-        e = torch.zeros_like(tt)
-        e[:, k] = steps_h[k]
-        fd = ((s.refine_forward(tt + e).double() - s.refine_forward(tt - e).double()) / (2 * steps_h[k])).cpu().numpy()
-        fd_err.append(np.abs(g[:, k] - fd) / np.maximum(np.abs(fd), 1e-1 * Pt / cells[k]))
-    fd_err = np.concatenate(fd_err)
+    fd = oracle_fd_check(wl, V, cells, peaks, th_chk, g, args.refine_fd_peaks,
+                         max(5.0, min(60.0, budget.left() - args.cpu_seconds - 20.0)))
+    log(f"refinement gradient vs FP64 central differences: {fd}")
     # truth: pulse-associated peaks (baseline, time overlap at f_ref, DM within 2 cells)
     t_ap = lay["t_ap_ms"]
     t_amb = cells[1] * srch["n_mbd"]
@@ -240,9 +317,7 @@ def refine_leg(args, wl, s, truth):
         "peak_steps_per_s": round(n * args.refine_steps / el, 1),
         "power_gain_median": round(float(np.median(P / np.maximum(
             s.refine_forward(torch.tensor(th0, dtype=torch.float64, device="cuda")).cpu().numpy(), 1e-30))), 5),
-        "grad_vs_central_diff_rel": {"median": float(np.median(fd_err)),
-                                     "p99": float(np.percentile(fd_err, 99)),
-                                     "max": float(np.max(fd_err))},
+        "grad_vs_fp64_central_diff": fd,
         "pulse_peaks": int(len(errs)),
         "within_0.05_cell": within,
         "median_abs_err_cells": med,
@@ -252,8 +327,11 @@ def refine_leg(args, wl, s, truth):
     }
 
 
-def run_form(args, wl, V, prec, dev, truth=None):
-    """Time `args.steps` full searches in one precision form; returns the
+def run_form(args, wl, V, prec, dev, truth, budget, reserve_after, headline):
+    """Full searches in one precision form: untimed warm-up (one when a step
+    is long), then as many timed steps as the budget leaves after
+    `reserve_after(step_s)` seconds for the legs still to come, at most
+    --steps (at most 2 for a form that is not the headline).  Returns the
     JSON record (without the CPU baseline)."""
     import torch
     from paper_1801_02391_amd import frbx
@@ -277,25 +355,36 @@ def run_form(args, wl, V, prec, dev, truth=None):
     N, J, P, M, R = lay["n_if"], lay["n_chan"], srch["sbd_pad"], srch["n_mbd"], srch["n_rate"]
     PJ = P * J
     cells = B * D * seg["total"] * R * PJ * M
-    log(f"segments/(b,d) {seg['total']}  cells/step {cells:.3e}")
+    log(f"{prec}: segments/(b,d) {seg['total']}  cells/step {cells:.3e}")
 
-    for i in range(args.warmup):
+    # warm-up: the first run (allocations, code load) is never timed; more
+    # warm-up runs only while a step is short
+    want_warm = max(1, args.warmup if headline else 1)
+    warm = []
+    while len(warm) < want_warm:
         t = time.perf_counter()
         s.run()
-        log(f"warmup {i + 1}/{args.warmup} {time.perf_counter() - t:.2f} s")
+        warm.append(time.perf_counter() - t)
+        log(f"{prec}: warmup {len(warm)}/{want_warm} {warm[-1]:.2f} s")
+        if warm[-1] > LONG_STEP_S or budget.left() - reserve_after(warm[-1]) < 2 * warm[-1]:
+            break
+    step_s = warm[-1]
+    max_steps = args.steps if headline else min(args.steps, 2)
+    n_steps = int(max(1, min(max_steps, (budget.left() - reserve_after(step_s)) // step_s)))
+    log(f"{prec}: timing {n_steps} step(s) of ~{step_s:.2f} s ({budget.left():.0f} s of budget left)")
     s.set_timing(True)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     tim = {"fringe_ms": 0.0, "n_fringe": 0, "fringe_units": 0, "dedisperse_ms": 0.0,
            "n_dedisperse": 0, "dedisperse_units": 0, "stats_ms": 0.0, "n_stats": 0,
            "dedisperse_bytes": 0}
-    for i in range(args.steps):
+    for i in range(n_steps):
         t = time.perf_counter()
         s.run()
         tt = s.timing()
         for k in tim:
             tim[k] += tt[k]
-        log(f"step {i + 1}/{args.steps} {time.perf_counter() - t:.2f} s "
+        log(f"{prec}: step {i + 1}/{n_steps} {time.perf_counter() - t:.2f} s "
             f"(fringe {tt['fringe_ms'] / 1e3:.2f} s, dedisperse {tt['dedisperse_ms'] / 1e3:.3f} s)")
     torch.cuda.synchronize()
     el = time.perf_counter() - t0
@@ -312,35 +401,44 @@ def run_form(args, wl, V, prec, dev, truth=None):
     n_det = len(cands)
     groups = s.groups()
     n_rep = sum(1 for g in groups if g["reported"])
-    refine = refine_leg(args, wl, s, truth) if (prec == "f32" and args.refine_peaks > 0) else None
+    refine = (refine_leg(args, wl, V, s, truth, budget)
+              if (prec == "f32" and args.refine_peaks > 0) else None)
 
     # dominant kernel: the fringe search
     cells_per_unit = R * PJ * M
     avg_ms = tim["fringe_ms"] / max(1, tim["n_fringe"])
     units_per_launch = tim["fringe_units"] / max(1, tim["n_fringe"])
+    rows = mbd_one_pass_rows(s, M) if prec == "f32" else 0
+    extra = {}
     if prec == "f32":
-        # FFT-form FP32 work on the vector ALUs
-        fpc = fringe_flops_per_cell(N, J, P, M)
+        # FFT-form FP32 work on the vector ALUs (the one-pass form's own work
+        # when it runs)
+        fpc = fringe_flops_per_cell(N, J, P, M, rows)
         bound, peak, kern = "alu", PEAK_FP32_TFLOPS, "fringe_kernel"
     else:
-        # matrix-core work: the real-embedded MBD GEMM, 2 x (2N) x (2M) flops
-        # per SBD bin, i.e. 8 N flops per cell per float16 product
-        fpc = 8 * N * (3 if prec == "f16x3" else 1)
+        # the method's matrix-core work: the real-embedded MBD GEMM, 2 x (2N)
+        # x (2M) flops per SBD bin, i.e. 8 N flops per cell; f16x3 issues it
+        # three times (high/low split), reported separately
+        fpc = 8 * N
         bound, peak, kern = "mfma", PEAK_FP16_MFMA_TFLOPS, "fringe_mfma_kernel"
     flops_launch = units_per_launch * cells_per_unit * fpc
     achieved = flops_launch / (avg_ms * 1e-3) / 1e12 if avg_ms > 0 else 0.0
+    if prec == "f32":
+        extra = {"attainable_peak_unpacked": PEAK_FP32_UNPACKED_TFLOPS,
+                 "frac_attainable": round(achieved / PEAK_FP32_UNPACKED_TFLOPS, 4)}
+    elif base_prec == "f16x3":
+        extra = {"issued_products": 3, "achieved_issued": round(3 * achieved, 3),
+                 "frac_issued": round(3 * achieved / peak, 4)}
     tkey = kern if prec == "f32" else f"{kern}_{base_prec}"
     traffic = measured_traffic(tkey, args.workload)
     roof = {"bound": bound, "achieved": round(achieved, 3), "peak": peak,
-            "unit": "TFLOP/s", "frac": round(achieved / peak, 4),
-            **({"attainable_peak_unpacked": PEAK_FP32_UNPACKED_TFLOPS,
-                "frac_attainable": round(achieved / PEAK_FP32_UNPACKED_TFLOPS, 4)} if prec == "f32" else {}),
+            "unit": "TFLOP/s", "frac": round(achieved / peak, 4), **extra,
             "traffic": traffic,
             **({"traffic_source": os.path.relpath(TRAFFIC_FILE, ROOT)} if traffic is not None else {}),
             "kernel": kern, "avg_launch_ms": round(avg_ms, 4),
-            "flops_per_cell": round(fpc, 2), "units_per_launch": units_per_launch}
+            "flops_per_cell": round(fpc, 3), "units_per_launch": units_per_launch}
     if prec == "f32":
-        roof.update(mbd_form(s))
+        roof.update(mbd_form(rows))
     # dedispersion kernel against HBM: every dedispersed spectrum written
     # once and every channel's input span read once per group of DM trials
     # (byte count reported by the library per launch)
@@ -357,12 +455,12 @@ def run_form(args, wl, V, prec, dev, truth=None):
 
     out = {
         "metric": "search cells/s (baseline x DM x window segment x rate x SBD x MBD)",
-        "value": cells * args.steps / el,
+        "value": cells * n_steps / el,
         "unit": "cells/s",
         "n_gpus": 1,
-        "steps": args.steps,
-        "warmup": args.warmup,
-        "ms_per_step": 1e3 * el / args.steps,
+        "steps": n_steps,
+        "warmup": len(warm),
+        "ms_per_step": 1e3 * el / n_steps,
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
@@ -587,6 +685,12 @@ def main():
     ap.add_argument("--refine-peaks", type=int, default=1024,
                     help="after the f32 search, refine this many top peaks (0: skip)")
     ap.add_argument("--refine-steps", type=int, default=20)
+    ap.add_argument("--refine-fd-peaks", type=int, default=256,
+                    help="peaks whose backward-kernel gradient is checked against central "
+                         "differences of the FP64 oracle")
+    ap.add_argument("--budget-s", type=float, default=420.0,
+                    help="wall-clock budget of the whole run from process start: the number of "
+                         "timed (full) steps of each form is cut to fit it and reported")
     ap.add_argument("--copy-calibration-mb", type=int, default=0,
                     help="after the timed steps, run one plain device copy (float32 "
                          "multiply by 1) of this many MiB, to calibrate HBM counters")
@@ -621,10 +725,39 @@ def main():
 
     forms = [args.precision] if args.only else [args.precision] + [p for p in ("f16x3", "f16", "f16-recheck")
                                                                    if p != args.precision]
-    results = {}
-    for prec in forms:
-        results[prec] = run_form(args, wl, V, prec, dev, truth)
+    budget = Budget(args.budget_s)
+    cpu_s = 0.0 if args.no_cpu_baseline else args.cpu_seconds + 5.0
+
+    def reserve(rest, base_step):
+        """Seconds the legs after the current one need: each remaining form
+        loads its input and runs three steps (one warm-up, two timed), the
+        f32 refinement leg, the CPU baseline."""
+        r = cpu_s
+        for f in rest:
+            r += LOAD_RESERVE_S + 3.0 * FORM_COST[f] / FORM_COST[args.precision] * base_step
+        return r
+
+    results, skipped = {}, {}
+    base_step = None
+    for i, prec in enumerate(forms):
+        rest = forms[i + 1:]
+        if i == 0:
+            refine_s = REFINE_RESERVE_S if (prec == "f32" and args.refine_peaks > 0) else 0.0
+            res = lambda st: reserve(rest, st) + refine_s
+        else:
+            res = lambda st: reserve(rest, base_step)
+            need = LOAD_RESERVE_S + 2.0 * FORM_COST[prec] / FORM_COST[args.precision] * base_step
+            if budget.left() - reserve(rest, base_step) < need:
+                skipped[prec] = f"not run: {budget.left():.0f} s of the {args.budget_s:.0f} s budget left"
+                log(f"{prec}: {skipped[prec]}")
+                continue
+        results[prec] = run_form(args, wl, V, prec, dev, truth, budget, res, headline=(i == 0))
+        if i == 0:
+            base_step = results[prec]["ms_per_step"] * 1e-3
     out = results[args.precision]
+    out["steps_requested"] = args.steps
+    out["warmup_requested"] = args.warmup
+    out["budget_s"] = args.budget_s
     base_c = {c[:4]: c[4] for c in out["_candidates"]}
     thr = srch["threshold"]
 
@@ -655,6 +788,7 @@ def main():
                 **({"recheck": r["recheck"]} if "recheck" in r else {}),
                 "candidates_vs_" + args.precision: compare(r)}
             for p, r in results.items() if p != args.precision}
+        out["precision_forms"].update({p: {"skipped": why} for p, why in skipped.items()})
     if args.cpu_full and args.precision == "f32":
         log("timing the oracle on the whole workload")
         out["cpu_full"] = cpu_full(wl, V, out["_candidates"])
@@ -663,7 +797,8 @@ def main():
         r.pop("_crossings", None)
     if not args.no_cpu_baseline:
         log("timing the oracle on a CPU sample")
-        out["cpu_baseline"] = cpu_baseline(wl, V[:1], args.cpu_seconds)
+        out["cpu_baseline"] = cpu_baseline(wl, V[:1], max(3.0, min(args.cpu_seconds, budget.left() - 5.0)))
+    out["wall_s"] = round(time.perf_counter() - T_START, 1)
     print(json.dumps(out), flush=True)
 
 

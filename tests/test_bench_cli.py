@@ -63,3 +63,16 @@ def test_algorithmic_flops_per_cell_of_the_roofline():
     # streaming: N = 16, J = 256, PJ = 1024, M = 256:
     # (819200 + 10485760 + 1048576 + 32768) / 262144
     assert bench.fringe_flops_per_cell(16, 256, 4, 256) == 12386304 / 262144 == 47.25
+
+
+def test_algorithmic_flops_per_cell_of_the_one_pass_form():
+    """The one-pass MBD form (compact IF lattice) is credited with the work it
+    does: per SBD bin, M / MB lanes each twiddle MB - 1 rows (6 flops) and
+    run one MB-point transform (5 MB log2 MB), instead of 5 M log2 M.
+    Single-baseline shape, N = 8, J = 32, PJ = 128, M = 256, MB = 16:
+    (35840 + 128 x 16 x (90 + 320) + 131072 + 2048) / 32768."""
+    sys.path.insert(0, ROOT)
+    import bench
+    assert bench.fringe_flops_per_cell(8, 32, 4, 256, 16) == 1008640 / 32768 == 30.78125
+    # below the two-pass count of the same shape
+    assert bench.fringe_flops_per_cell(8, 32, 4, 256) > 30.78125
