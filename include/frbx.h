@@ -25,7 +25,8 @@
  *   build the grid tables on the device after a grid changed
  *   (frbx_get_segments, frbx_get_lattice, frbx_get_ap_offsets,
  *   frbx_refine_cells); it is reused across calls and freed by
- *   frbx_destroy.  No entry point frees memory the caller owns.
+ *   frbx_destroy.  frbx_run_cube_noalloc allocates nothing (it runs in a
+ *   fixed per-GPU workspace).  No entry point frees memory the caller owns.
  */
 #ifndef FRBX_H
 #define FRBX_H
@@ -225,6 +226,27 @@ frbx_status frbx_load_e4m3(frbx_ctx *ctx, const void *codes, const float *scale,
  * multi-window filter, best-DM merge and cross-baseline matching on the
  * host. */
 frbx_status frbx_run(frbx_ctx *ctx);
+
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the device
+ * part of frbx_run -- dedispersion and the fringe search of every (baseline,
+ * DM trial, segment) -- with no allocation, enqueued on the context's stream
+ * without waiting.  It writes the power cube as frbx_get_power_cube returns
+ * it after frbx_run: power float32 and idx int32, both DEVICE buffers of the
+ * caller, [B][D][segments] with cap elements each (cap < needed:
+ * FRBX_E_RANGE with *n = needed; cap = 0 is a size query).  No statistics,
+ * crossings or detections, no float32 re-evaluation, no timing.
+ * The dedispersed DM tiles go through a fixed workspace of 64 MiB that the
+ * library holds on every GPU it runs on until the process ends (looked up
+ * at frbx_create); one DM trial's tile, (K - dk_max) x N x J x 8 bytes, must
+ * fit in it, else FRBX_E_INVAL.  Every call on one GPU shares that
+ * workspace: calls that overlap on one GPU (two streams, two threads) race
+ * and must be serialised by the caller.  The input must be loaded and the
+ * grid tables built after the last setter (frbx_get_segments or frbx_run):
+ * FRBX_E_STATE otherwise, since building them allocates.  The results equal
+ * frbx_run's cube bit for bit. */
+frbx_status frbx_run_cube_noalloc(frbx_ctx *ctx, float *power, int32_t *idx, int64_t cap,
+                                  int64_t *n);
 
 /* Segment layout of the current grids: dk_max (largest AP offset over all DM
  * trials), per window its hop and segment count Q (arrays of the number of

@@ -105,6 +105,9 @@ struct frbx_ctx {
   unsigned long long *d_ncross = nullptr;
   int64_t cross_cap = 0;
   size_t w_budget = size_t(6) << 30;
+  // this device's copy of the no-alloc workspace (looked up at create)
+  void *d_noalloc = nullptr;
+  std::string noalloc_err;
 
   // timing
   bool timing = false;
@@ -721,6 +724,14 @@ frbx_status frbx_create(const frbx_layout *L, int device, void *hip_stream, frbx
   c->tau0.assign(size_t(c->B) * c->N, 0.0);
   c->phi0.assign(size_t(c->B) * c->N, 0.0);
   if (const char *e = std::getenv("FRBX_W_BUDGET_MB")) c->w_budget = size_t(std::atoll(e)) << 20;
+  // the device address of this GPU's no-alloc workspace, looked up once per
+  // device with the device current (its failure only disables
+  // frbx_run_cube_noalloc)
+  const hipError_t we = frbx::noalloc_workspace(device, &c->d_noalloc);
+  if (we != hipSuccess) {
+    c->d_noalloc = nullptr;
+    c->noalloc_err = std::string("no-alloc workspace lookup: ") + hipGetErrorString(we);
+  }
   *out = c;
   return FRBX_OK;
 }
@@ -1041,6 +1052,93 @@ frbx_status recheck_pass(frbx_ctx *c, const PassSpec &ps, frbx::StatsArgs &st, s
   return c->hip(frbx::launch_fringe_list(J, M, fa, lds, int(n), c->stream), "recheck launch");
 }
 
+// Dedispersion and fringe search of every (baseline, DM tile): the DM
+// trials are taken dt at a time through the dedispersed-tile buffer wbuf
+// ([dt][k_eff][N J]), and every segment's peak goes into the cube
+// power / pidx ([B][D][S]).
+frbx_status search_tiles(frbx_ctx *c, const PassSpec &ps, float2 *wbuf, int dt, float *power, int32_t *pidx) {
+  const int B = c->B, D = c->n_dm, NJ = c->N * c->J, nw = int(c->windows.size());
+  const int64_t S = ps.S;
+  const int64_t k_eff = ps.K - c->dk_max;
+  const int J = c->J, M = c->n_mbd;
+  frbx_status s;
+  const int n_pass = c->precision == FRBX_PREC_F16X3 ? 3 : 1;
+  const bool use_mfma = c->precision != FRBX_PREC_F32;
+  const size_t lds = use_mfma ? frbx::fringe_mfma_lds_bytes(J, c->N, c->sbd_pad, n_pass)
+                              : frbx::fringe_lds_bytes(J, M, c->N, c->sbd_pad);
+  const float scale = mfma_scale(c);
+  const size_t in_bytes = ps.vis_f16 ? 4 : 8;
+  if (S > 0 && k_eff > 0) {
+    for (int b = 0; b < B; ++b) {
+      for (int d0 = 0; d0 < D; d0 += dt) {
+        const int ndt = std::min(dt, D - d0);
+        frbx::DedisperseArgs da{};
+        da.vis = static_cast<const char *>(ps.vis) + size_t(b) * NJ * size_t(ps.stride) * in_bytes;
+        da.in_f16 = ps.vis_f16;
+        da.n_frames = ps.K;
+        da.row_stride = ps.stride;
+        da.dk = c->d_dk;
+        da.d0 = d0;
+        da.n_dt = ndt;
+        da.cal = c->d_cal + size_t(b) * NJ;
+        da.out = wbuf;
+        da.k_eff = k_eff;
+        da.nj = NJ;
+        da.group = c->dd_group;
+        int sp = c->span_begin(1, int64_t(ndt) * k_eff);
+        if (sp >= 0) {
+          // writes: ndt x k_eff spectra; reads: each channel's span of
+          // k_eff + (offset spread of the group) APs once per group
+          int64_t bytes = int64_t(ndt) * k_eff * NJ * 8;
+          for (int g0 = 0; g0 < ndt; g0 += c->dd_group) {
+            const int g1 = std::min(ndt, g0 + c->dd_group) - 1;
+            const int32_t *a0 = c->dk.data() + size_t(d0 + g0) * NJ, *a1 = c->dk.data() + size_t(d0 + g1) * NJ;
+            for (int i = 0; i < NJ; ++i) bytes += (k_eff + (a1[i] - a0[i])) * int64_t(in_bytes);
+          }
+          c->spans[sp].bytes = bytes;
+        }
+        if ((s = c->hip(frbx::launch_dedisperse(da, c->stream), "dedisperse launch")) != FRBX_OK) return s;
+        c->span_end(sp);
+        frbx::FringeArgs fa{};
+        fa.w = wbuf;
+        fa.w_dm_stride = k_eff * NJ;
+        fa.n_if = c->N;
+        fa.n_rate = c->n_rate;
+        fa.sbd_pad = c->sbd_pad;
+        fa.n_win = nw;
+        for (int w = 0; w < nw; ++w) {
+          fa.win_len[w] = c->windows[w];
+          fa.win_hop[w] = c->hop[w];
+          fa.win_off[w] = ps.off[w];
+          fa.win_k0[w] = ps.k0[w];
+          fa.rate_off[w] = c->rate_off[w];
+        }
+        fa.seg_total = int(S);
+        fa.n_dt = ndt;
+        fa.rate_ph = c->d_rate;
+        fa.tw_sbd = c->d_tw_sbd;
+        fa.pre_sbd = c->d_pre;
+        fa.tw_mbd = c->d_tw_mbd;
+        fa.mbd_row = c->d_row;
+        fa.mbd_pos = c->mbd_pos.empty() ? nullptr : c->d_pos;
+        fa.power = power + (size_t(b) * D + d0) * S;
+        fa.pidx = pidx + (size_t(b) * D + d0) * S;
+        fa.dump = nullptr;
+        fa.mfma_b_hi = c->d_mfma_hi;
+        fa.mfma_b_lo = c->d_mfma_lo;
+        fa.mfma_scale = scale;
+        sp = c->span_begin(0, int64_t(ndt) * S);
+        const hipError_t le = use_mfma
+                                  ? frbx::launch_fringe_mfma(J, c->N, n_pass, fa, lds, int(ndt * S), c->stream)
+                                  : frbx::launch_fringe(J, M, fa, lds, int(ndt * S), c->stream);
+        if ((s = c->hip(le, "fringe launch")) != FRBX_OK) return s;
+        c->span_end(sp);
+      }
+    }
+  }
+  return FRBX_OK;
+}
+
 frbx_status device_pass(frbx_ctx *c, const PassSpec &ps, std::vector<DevCrossing> &hc) {
   frbx_status s;
   const int B = c->B, D = c->n_dm, NJ = c->N * c->J, nw = int(c->windows.size());
@@ -1067,81 +1165,8 @@ frbx_status device_pass(frbx_ctx *c, const PassSpec &ps, std::vector<DevCrossing
       return c->fail(FRBX_E_NOMEM, "device allocation failed");
     c->cross_cap = want_cap;
   }
-  const int J = c->J, M = c->n_mbd;
-  const int n_pass = c->precision == FRBX_PREC_F16X3 ? 3 : 1;
   const bool use_mfma = c->precision != FRBX_PREC_F32;
-  const size_t lds = use_mfma ? frbx::fringe_mfma_lds_bytes(J, c->N, c->sbd_pad, n_pass)
-                              : frbx::fringe_lds_bytes(J, M, c->N, c->sbd_pad);
-  const float scale = mfma_scale(c);
-  const size_t in_bytes = ps.vis_f16 ? 4 : 8;
-  if (S > 0 && k_eff > 0) {
-    for (int b = 0; b < B; ++b) {
-      for (int d0 = 0; d0 < D; d0 += c->dt) {
-        const int ndt = std::min(c->dt, D - d0);
-        frbx::DedisperseArgs da{};
-        da.vis = static_cast<const char *>(ps.vis) + size_t(b) * NJ * size_t(ps.stride) * in_bytes;
-        da.in_f16 = ps.vis_f16;
-        da.n_frames = ps.K;
-        da.row_stride = ps.stride;
-        da.dk = c->d_dk;
-        da.d0 = d0;
-        da.n_dt = ndt;
-        da.cal = c->d_cal + size_t(b) * NJ;
-        da.out = c->d_w;
-        da.k_eff = k_eff;
-        da.nj = NJ;
-        da.group = c->dd_group;
-        int sp = c->span_begin(1, int64_t(ndt) * k_eff);
-        if (sp >= 0) {
-          // writes: ndt x k_eff spectra; reads: each channel's span of
-          // k_eff + (offset spread of the group) APs once per group
-          int64_t bytes = int64_t(ndt) * k_eff * NJ * 8;
-          for (int g0 = 0; g0 < ndt; g0 += c->dd_group) {
-            const int g1 = std::min(ndt, g0 + c->dd_group) - 1;
-            const int32_t *a0 = c->dk.data() + size_t(d0 + g0) * NJ, *a1 = c->dk.data() + size_t(d0 + g1) * NJ;
-            for (int i = 0; i < NJ; ++i) bytes += (k_eff + (a1[i] - a0[i])) * int64_t(in_bytes);
-          }
-          c->spans[sp].bytes = bytes;
-        }
-        if ((s = c->hip(frbx::launch_dedisperse(da, c->stream), "dedisperse launch")) != FRBX_OK) return s;
-        c->span_end(sp);
-        frbx::FringeArgs fa{};
-        fa.w = c->d_w;
-        fa.w_dm_stride = k_eff * NJ;
-        fa.n_if = c->N;
-        fa.n_rate = c->n_rate;
-        fa.sbd_pad = c->sbd_pad;
-        fa.n_win = nw;
-        for (int w = 0; w < nw; ++w) {
-          fa.win_len[w] = c->windows[w];
-          fa.win_hop[w] = c->hop[w];
-          fa.win_off[w] = ps.off[w];
-          fa.win_k0[w] = ps.k0[w];
-          fa.rate_off[w] = c->rate_off[w];
-        }
-        fa.seg_total = int(S);
-        fa.n_dt = ndt;
-        fa.rate_ph = c->d_rate;
-        fa.tw_sbd = c->d_tw_sbd;
-        fa.pre_sbd = c->d_pre;
-        fa.tw_mbd = c->d_tw_mbd;
-        fa.mbd_row = c->d_row;
-        fa.mbd_pos = c->mbd_pos.empty() ? nullptr : c->d_pos;
-        fa.power = c->d_power + (size_t(b) * D + d0) * S;
-        fa.pidx = c->d_pidx + (size_t(b) * D + d0) * S;
-        fa.dump = nullptr;
-        fa.mfma_b_hi = c->d_mfma_hi;
-        fa.mfma_b_lo = c->d_mfma_lo;
-        fa.mfma_scale = scale;
-        sp = c->span_begin(0, int64_t(ndt) * S);
-        const hipError_t le = use_mfma
-                                  ? frbx::launch_fringe_mfma(J, c->N, n_pass, fa, lds, int(ndt * S), c->stream)
-                                  : frbx::launch_fringe(J, M, fa, lds, int(ndt * S), c->stream);
-        if ((s = c->hip(le, "fringe launch")) != FRBX_OK) return s;
-        c->span_end(sp);
-      }
-    }
-  }
+  if ((s = search_tiles(c, ps, c->d_w, c->dt, c->d_power, c->d_pidx)) != FRBX_OK) return s;
   // Eq. 6 statistics and threshold crossings
   frbx::StatsArgs st{};
   st.power = c->d_power;
@@ -1238,6 +1263,48 @@ frbx_status frbx_run(frbx_ctx *c) {
               c->dets, c->groups);
   c->have = true;
   return FRBX_OK;
+}
+
+frbx_status frbx_run_cube_noalloc(frbx_ctx *c, float *power, int32_t *idx, int64_t cap, int64_t *n) {
+  if (!c) return FRBX_E_INVAL;
+  if (!c->loaded) return c->fail(FRBX_E_STATE, "frbx_run_cube_noalloc before frbx_load");
+  if (c->dirty)
+    return c->fail(FRBX_E_STATE, "grid tables not built: call frbx_get_segments (or frbx_run) after the last "
+                                 "setter; frbx_run_cube_noalloc builds nothing");
+  if (!c->d_noalloc) return c->fail(FRBX_E_DEVICE, c->noalloc_err.empty() ? "no-alloc workspace unavailable" : c->noalloc_err);
+  if (hipSetDevice(c->device) != hipSuccess) return c->fail(FRBX_E_DEVICE, "hipSetDevice failed");
+  const int D = c->n_dm, NJ = c->N * c->J;
+  const int64_t S = c->seg_total;
+  const int64_t len = int64_t(c->B) * D * S;
+  if (n) *n = len;
+  if (cap < len) return c->fail(FRBX_E_RANGE, "output capacity below B x D x segments");
+  if (len == 0) return FRBX_OK;
+  if (!power || !idx) return c->fail(FRBX_E_INVAL, "null output pointer");
+  const int64_t k_eff = c->K - c->dk_max;
+  const size_t per_dm = size_t(k_eff) * NJ * sizeof(float2);
+  if (per_dm > frbx::kNoAllocBytes)
+    return c->fail(FRBX_E_INVAL, "one DM trial's dedispersed tile (" + std::to_string(per_dm) +
+                                     " bytes) exceeds the no-alloc workspace (" +
+                                     std::to_string(frbx::kNoAllocBytes) + " bytes)");
+  int dt = int(std::min<size_t>(size_t(D), frbx::kNoAllocBytes / per_dm));
+  while (dt > 1 && int64_t(dt) * S > (int64_t(1) << 31) - 1) dt /= 2;
+  if (int64_t(dt) * S > (int64_t(1) << 31) - 1) return c->fail(FRBX_E_INVAL, "too many segments per DM trial");
+  const int nw = int(c->windows.size());
+  PassSpec ps;
+  ps.vis = c->d_vis;
+  ps.vis_f16 = c->vis_f16;
+  ps.K = c->K;
+  ps.stride = c->K;
+  ps.k0.assign(nw, 0);
+  ps.nq = c->nseg;
+  ps.off = c->segoff;
+  ps.S = S;
+  // no timing events (their pool may grow): launches only
+  const bool tm = c->timing;
+  c->timing = false;
+  const frbx_status s = search_tiles(c, ps, static_cast<float2 *>(c->d_noalloc), dt, power, idx);
+  c->timing = tm;
+  return s;
 }
 
 frbx_status frbx_stream_begin(frbx_ctx *c, int64_t chunk_frames) {

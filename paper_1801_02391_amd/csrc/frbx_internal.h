@@ -199,4 +199,13 @@ hipError_t launch_refine(int mode, const RefineArgs &a, hipStream_t s);
 hipError_t launch_absmax(const void *vis, int64_t n, int in_f16, unsigned int *out,
                          hipStream_t s);
 
+// Workspace of the search variant that allocates nothing: a file-scope
+// device array of kNoAllocBytes on every GPU the library runs on.
+// noalloc_workspace(device) must be called with `device` current; the first
+// call on a device looks up that device's copy of the array
+// (hipGetSymbolAddress) and later calls return the same address.
+constexpr size_t kNoAllocBytes = size_t(64) << 20;
+constexpr int kMaxDevices = 64;
+hipError_t noalloc_workspace(int device, void **ptr);
+
 }  // namespace frbx

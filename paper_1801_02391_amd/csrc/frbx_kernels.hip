@@ -38,9 +38,16 @@
 
 #include <algorithm>
 #include <cmath>
+#include <mutex>
 #include <type_traits>
 
 #include "frbx_internal.h"
+
+// Workspace of the search variant that allocates nothing (dedispersed DM
+// tiles): every GPU holds its own copy of this array, at its own address,
+// from module load until the process ends.  In host code the name is only a
+// host-side stand-in; the device address comes from noalloc_workspace().
+static __device__ __align__(256) unsigned char scratch[frbx::kNoAllocBytes];
 
 namespace frbx {
 namespace {
@@ -1448,6 +1455,26 @@ hipError_t launch_carry(const float2 *src, float2 *dst, int n_ch, int64_t frames
   hipLaunchKernelGGL(carry_kernel, dim3(unsigned(bx), gy), dim3(kBlock), 0, s, src, dst, n_ch, frames,
                      from, n);
   return hipGetLastError();
+}
+
+hipError_t noalloc_workspace(int device, void **ptr) {
+  static std::mutex mu;
+  static void *addr[kMaxDevices] = {};
+  if (!ptr || device < 0 || device >= kMaxDevices) return hipErrorInvalidValue;
+  std::lock_guard<std::mutex> lock(mu);
+  if (!addr[device]) {
+    int cur = -1;
+    hipError_t e = hipGetDevice(&cur);
+    if (e != hipSuccess) return e;
+    if (cur != device) return hipErrorInvalidDevice;   // the caller makes `device` current
+    void *p = nullptr;
+    e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return e;
+    if (!p) return hipErrorInvalidSymbol;
+    addr[device] = p;
+  }
+  *ptr = addr[device];
+  return hipSuccess;
 }
 
 hipError_t launch_absmax(const void *vis, int64_t n, int in_f16, unsigned int *out, hipStream_t s) {

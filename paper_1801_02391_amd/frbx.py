@@ -73,6 +73,7 @@ _SIGS = {
     "frbx_load_f16": ([_P, _P, C.c_int], C.c_int),
     "frbx_set_precision": ([_P, C.c_int32], C.c_int),
     "frbx_run": ([_P], C.c_int),
+    "frbx_run_cube_noalloc": ([_P, _P, _P, C.c_int64, C.POINTER(C.c_int64)], C.c_int),
     "frbx_get_segments": ([_P, _P, _P, _P, _P], C.c_int),
     "frbx_get_lattice": ([_P, _P, _P, _P], C.c_int),
     "frbx_set_recheck": ([_P, C.c_double], C.c_int),
@@ -314,6 +315,23 @@ class Search:
 
     def run(self):
         self._chk(lib().frbx_run(self._h), "run")
+
+    def run_cube_noalloc(self, power, idx):
+        """frbx_run_cube_noalloc into caller-owned contiguous GPU tensors
+        (power float32, idx int32, each of B * D * segments elements or
+        more); enqueued on the context's stream.  Returns the element count
+        written."""
+        torch = self._torch
+        if not (isinstance(power, torch.Tensor) and isinstance(idx, torch.Tensor)
+                and power.device.type == "cuda" and idx.device.type == "cuda"
+                and power.dtype == torch.float32 and idx.dtype == torch.int32
+                and power.is_contiguous() and idx.is_contiguous()):
+            raise FrbxError(E_INVAL, "power (float32) and idx (int32) must be contiguous GPU tensors")
+        n = C.c_int64(0)
+        self._chk(lib().frbx_run_cube_noalloc(self._h, _P(power.data_ptr()), _P(idx.data_ptr()),
+                                              min(power.numel(), idx.numel()), C.byref(n)),
+                  "run_cube_noalloc")
+        return n.value
 
     # ------------------------------------------------------------- results
     def segments(self):
