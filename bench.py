@@ -30,6 +30,9 @@ PEAK_FP32_TFLOPS = 157.3     # MI355X vector FP32 (packed), published
 PEAK_FP32_UNPACKED_TFLOPS = 78.6
 PEAK_FP16_MFMA_TFLOPS = 2500.0  # MI355X dense FP16 matrix, published
 PEAK_HBM_GBS = 8000.0        # MI355X HBM3E, published
+# channel counts for which the f16 form runs its SBD transform on the matrix
+# cores as well (the library's fringe_gemm_kernel)
+SBD_GEMM_CHANNELS = (16, 32, 64, 128)
 
 
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_vgos_6bl_20000.txt")
@@ -418,9 +421,16 @@ def run_form(args, wl, V, prec, dev, truth, budget, reserve_after, headline):
     else:
         # the method's matrix-core work: the real-embedded MBD GEMM, 2 x (2N)
         # x (2M) flops per SBD bin, i.e. 8 N flops per cell; f16x3 issues it
-        # three times (high/low split), reported separately
+        # three times (high/low split), reported separately.  The f16 form
+        # also runs the SBD transform as a real-embedded GEMM where J <= 128:
+        # per (segment, rate) P sub-grids of 2 x (2J) x (2J) x N flops over
+        # PJ M cells, 8 N J / M flops per cell.
         fpc = 8 * N
-        bound, peak, kern = "mfma", PEAK_FP16_MFMA_TFLOPS, "fringe_mfma_kernel"
+        kern = "fringe_mfma_kernel"
+        if base_prec == "f16" and J in SBD_GEMM_CHANNELS:
+            fpc += 8 * N * J / M
+            kern = "fringe_gemm_kernel"
+        bound, peak = "mfma", PEAK_FP16_MFMA_TFLOPS
     flops_launch = units_per_launch * cells_per_unit * fpc
     achieved = flops_launch / (avg_ms * 1e-3) / 1e12 if avg_ms > 0 else 0.0
     if prec == "f32":

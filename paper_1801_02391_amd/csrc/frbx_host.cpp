@@ -87,6 +87,7 @@ struct frbx_ctx {
   float vis_absmax = 0.f;
   bool loaded = false;
   void *d_mfma_hi = nullptr, *d_mfma_lo = nullptr;
+  void *d_sbd_a = nullptr;   // float16 form: SBD DFT matrix as MFMA A operands
   unsigned int *d_absmax = nullptr;
   int32_t *d_dk = nullptr;
   float2 *d_cal = nullptr, *d_rate = nullptr, *d_tw_sbd = nullptr, *d_pre = nullptr,
@@ -211,6 +212,7 @@ struct frbx_ctx {
     dfree(d_scale);
     dfree(d_mfma_hi);
     dfree(d_mfma_lo);
+    dfree(d_sbd_a);
     dfree(d_absmax);
     dfree(d_dk);
     dfree(d_cal);
@@ -359,6 +361,25 @@ float2 cis_cycles(double x) {
                      static_cast<float>(-std::sin(kTwoPi * r)));
 }
 
+// The float16 form runs both transforms on the matrix cores where the
+// shape allows (n_chan <= 128); otherwise its SBD stays on the vector ALUs.
+bool use_gemm(const frbx_ctx *c) {
+  return c->precision == FRBX_PREC_F16 && frbx::fringe_gemm_supported(c->J, c->n_mbd, c->N, c->sbd_pad);
+}
+
+// The matrix-core fringe launch of the current precision (both transforms
+// on the matrix cores, or the MBD only).
+hipError_t launch_matrix_core(const frbx_ctx *c, frbx::FringeArgs &fa, int grid) {
+  if (use_gemm(c)) {
+    fa.sbd_a = c->d_sbd_a;
+    return frbx::launch_fringe_gemm(c->J, c->N, fa, frbx::fringe_gemm_lds_bytes(c->J, c->N, c->sbd_pad), grid,
+                                    c->stream);
+  }
+  const int n_pass = c->precision == FRBX_PREC_F16X3 ? 3 : 1;
+  return frbx::launch_fringe_mfma(c->J, c->N, n_pass, fa, frbx::fringe_mfma_lds_bytes(c->J, c->N, c->sbd_pad, n_pass),
+                                  grid, c->stream);
+}
+
 frbx_status prepare(frbx_ctx *c) {
   if (!c->dirty) return FRBX_OK;
   c->rbegun = false;  // a refinement's cells and tables follow the grids
@@ -505,6 +526,28 @@ frbx_status prepare(frbx_ctx *c) {
           }
     if ((s = up(c->d_mfma_hi, bh)) != FRBX_OK) return s;
     if ((s = up(c->d_mfma_lo, bl)) != FRBX_OK) return s;
+    if (use_gemm(c)) {
+      // Real-embedded J-point DFT of the SBD sub-grids as MFMA A operands:
+      // row 2a (+1) gives Re (Im) X(a), column 2j (+1) multiplies Re (Im) Y(j),
+      // so the 2 x 2 block of (a, j) is [cos, sin; -sin, cos] of 2 pi j a / J.
+      // Per-lane order of v_mfma_f32_16x16x32_f16: lane ln, element e of
+      // K-chunk kc of row tile rt is row 16 rt + ln % 16, column
+      // 32 kc + 8 (ln / 16) + e.
+      const int SRT = 2 * J / 16, KC = J / 16;
+      std::vector<_Float16> fa(size_t(SRT) * KC * 64 * 8);
+      for (int rt = 0; rt < SRT; ++rt)
+        for (int kc = 0; kc < KC; ++kc)
+          for (int ln = 0; ln < 64; ++ln)
+            for (int e = 0; e < 8; ++e) {
+              const int row = 16 * rt + ln % 16, col = 32 * kc + 8 * (ln / 16) + e;
+              const int aa = row / 2, re_im = row % 2, j = col / 2, comp = col % 2;
+              const double th = kTwoPi * double((int64_t(j) * aa) % J) / J;
+              const double cs = std::cos(th), sn = std::sin(th);
+              const double v = re_im == 0 ? (comp == 0 ? cs : sn) : (comp == 0 ? -sn : cs);
+              fa[((size_t(rt) * KC + kc) * 64 + ln) * 8 + e] = static_cast<_Float16>(v);
+            }
+      if ((s = up(c->d_sbd_a, fa)) != FRBX_OK) return s;
+    }
   }
   c->dirty = false;
   return FRBX_OK;
@@ -1062,10 +1105,8 @@ frbx_status search_tiles(frbx_ctx *c, const PassSpec &ps, float2 *wbuf, int dt, 
   const int64_t k_eff = ps.K - c->dk_max;
   const int J = c->J, M = c->n_mbd;
   frbx_status s;
-  const int n_pass = c->precision == FRBX_PREC_F16X3 ? 3 : 1;
   const bool use_mfma = c->precision != FRBX_PREC_F32;
-  const size_t lds = use_mfma ? frbx::fringe_mfma_lds_bytes(J, c->N, c->sbd_pad, n_pass)
-                              : frbx::fringe_lds_bytes(J, M, c->N, c->sbd_pad);
+  const size_t lds = frbx::fringe_lds_bytes(J, M, c->N, c->sbd_pad);
   const float scale = mfma_scale(c);
   const size_t in_bytes = ps.vis_f16 ? 4 : 8;
   if (S > 0 && k_eff > 0) {
@@ -1128,9 +1169,8 @@ frbx_status search_tiles(frbx_ctx *c, const PassSpec &ps, float2 *wbuf, int dt, 
         fa.mfma_b_lo = c->d_mfma_lo;
         fa.mfma_scale = scale;
         sp = c->span_begin(0, int64_t(ndt) * S);
-        const hipError_t le = use_mfma
-                                  ? frbx::launch_fringe_mfma(J, c->N, n_pass, fa, lds, int(ndt * S), c->stream)
-                                  : frbx::launch_fringe(J, M, fa, lds, int(ndt * S), c->stream);
+        const hipError_t le = use_mfma ? launch_matrix_core(c, fa, int(ndt * S))
+                                       : frbx::launch_fringe(J, M, fa, lds, int(ndt * S), c->stream);
         if ((s = c->hip(le, "fringe launch")) != FRBX_OK) return s;
         c->span_end(sp);
       }
@@ -1588,9 +1628,9 @@ frbx_status frbx_dump_segment(frbx_ctx *c, int32_t b, int32_t d, int32_t w, int6
   fa.mfma_b_lo = c->d_mfma_lo;
   fa.mfma_scale = mfma_scale(c);
   hipError_t le;
+  (void)n_pass;
   if (c->precision != FRBX_PREC_F32) {
-    const size_t lds = frbx::fringe_mfma_lds_bytes(c->J, c->N, c->sbd_pad, n_pass);
-    le = frbx::launch_fringe_mfma(c->J, c->N, n_pass, fa, lds, 1, c->stream);
+    le = launch_matrix_core(c, fa, 1);
   } else {
     const size_t lds = frbx::fringe_lds_bytes(c->J, c->n_mbd, c->N, c->sbd_pad);
     le = frbx::launch_fringe(c->J, c->n_mbd, fa, lds, 1, c->stream);

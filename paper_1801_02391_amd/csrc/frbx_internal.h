@@ -94,6 +94,10 @@ struct FringeArgs {
   const void *mfma_b_hi;
   const void *mfma_b_lo;
   float mfma_scale;
+  // matrix-core SBD transform (float16 form): the real-embedded J-point DFT
+  // matrix as MFMA A operands, [2J/16 row tiles][J/16 K chunks][64 lanes] x
+  // 8 halves
+  const void *sbd_a;
 };
 
 struct StatsArgs {
@@ -134,6 +138,15 @@ hipError_t launch_fringe_mfma(int n_chan, int n_if, int n_pass, const FringeArgs
                               size_t lds_bytes, int grid, hipStream_t s);
 size_t fringe_mfma_lds_bytes(int n_chan, int n_if, int sbd_pad, int n_pass);
 bool fringe_mfma_supported(int n_chan, int n_mbd, int n_if, int sbd_pad, int n_pass);
+
+// matrix-core fringe kernel with both transforms on the matrix cores
+// (float16 form): 512 threads per segment; n_chan in {16, 32, 64, 128},
+// n_mbd = 256, n_if <= 32
+constexpr int kBlockGemm = 512;
+hipError_t launch_fringe_gemm(int n_chan, int n_if, const FringeArgs &a, size_t lds_bytes, int grid,
+                              hipStream_t s);
+size_t fringe_gemm_lds_bytes(int n_chan, int n_if, int sbd_pad);
+bool fringe_gemm_supported(int n_chan, int n_mbd, int n_if, int sbd_pad);
 
 // out[d][s] = sum over the listed baselines of power[b][d][s]
 hipError_t launch_cube_sum(const float *power, int64_t bl_stride, const int32_t *baselines,

@@ -20,6 +20,9 @@
 //                      real-embedded complex GEMM on the matrix cores (float16
 //                      operands, float32 accumulation; one product, or three
 //                      of a high/low split for float32-grade results).
+//   fringe_gemm_kernel the float16 form with the SBD transform on the matrix
+//                      cores as well (a J-point DFT GEMM per SBD sub-grid),
+//                      eight waves per segment.
 //   stats_kernel       Eq. 6 and the threshold of Sec. 2.4.1 per (baseline,
 //                      DM trial, window): float64 two-pass mean / population
 //                      deviation, ordered compaction of the crossings.
@@ -232,15 +235,18 @@ __device__ __forceinline__ void segment_sum(float2 (&y)[JA], const float2 *wd, c
   const int NJ = N * J;
   const float2 *src = wd + n1 * J + i2s;
   const float2 *ph = rph + (r * N + n1) * l;
-  for (int u = 0; u < l; ++u) {
-    if (R > 1) {
+  // the rate test outside the AP loop
+  if (R > 1) {
+    for (int u = 0; u < l; ++u) {
       const float2 p = ph[u];
       static_for<0, JA>([&](auto i) {
         constexpr int ii = decltype(i)::value;
         const float2 v = src[int64_t(u) * NJ + JB * ii];
         y[ii] = cadd(y[ii], cmul(v, p));
       });
-    } else {
+    }
+  } else {
+    for (int u = 0; u < l; ++u) {
       static_for<0, JA>([&](auto i) {
         constexpr int ii = decltype(i)::value;
         y[ii] = cadd(y[ii], src[int64_t(u) * NJ + JB * ii]);
@@ -894,6 +900,335 @@ __global__ __launch_bounds__(kBlock) void fringe_mfma_kernel(FringeArgs a) {
   }
 }
 
+// ------------------------------------- matrix-core fringe kernel, GEMM SBD
+// The float16 form with both transforms of Eq. 5 on the matrix cores, eight
+// waves per segment.
+//   SBD (Sec. 5.1, f_j term): for each of the P sub-grids c of the
+//   zero-padded transform (bins s' = c + P a), the J-point DFT over the
+//   frequency points of the rotated, scaled segment sums,
+//     X_c[a][n] = sum_j w_J^{j a} (w_PJ^{j c} scale Y(n, j)),
+//   as a real-embedded GEMM: the constant DFT matrix is the A operand (rows
+//   (a, Re/Im), K = (j, Re/Im), held in registers), the sums the B operand
+//   (columns n, staged in LDS as float16).  One v_mfma_f32_16x16x32_f16 per
+//   16 rows x 16 IFs x 32 K.
+//   MBD (f0^n term): as in fringe_mfma_kernel, with each wave owning 32 MBD
+//   columns (two Re and two Im tiles of the constant B operand).
+// The SBD output goes from the accumulators to float16 A-operand rows of
+// the MBD GEMM in LDS.  The sub-grids are taken `batch` at a time (as many
+// as keep the LDS plan near 76 KiB, two work-groups per CU): two barriers per
+// (rate, batch).
+template <int J, int NK>
+__host__ __device__ inline int gemm_batch(int sbd_pad) {
+  constexpr int YB = 16 * NK * (2 * J + 8) * 2;   // bytes of one sub-grid's sums
+  constexpr int AB = J * (32 * NK + 8) * 2;       // bytes of one sub-grid's MBD A rows
+  int pb = sbd_pad;
+  while (pb > 1 && sbd_pad * J * 8 + pb * (YB + AB) > 76 * 1024) pb >>= 1;
+  return pb;
+}
+
+template <int J, int NK>
+__host__ __device__ inline void gemm_lds_plan(int sbd_pad, int &y_off, int &a_off, int &total_bytes) {
+  constexpr int YS = 2 * J + 8;     // sums row stride in halves (+16 B against bank conflicts)
+  constexpr int AS = 32 * NK + 8;   // MBD A row stride in halves
+  const int pb = gemm_batch<J, NK>(sbd_pad);
+  y_off = sbd_pad * J * 8;          // after the scaled twiddles [PJ] float2
+  a_off = y_off + pb * 16 * NK * YS * 2;
+  total_bytes = a_off + pb * J * AS * 2;
+}
+
+template <int J, int NK, bool DUMP>
+__global__ __launch_bounds__(kBlockGemm) void fringe_gemm_kernel(FringeArgs a) {
+  constexpr int M = 256;
+  constexpr int YS = 2 * J + 8, AS = 32 * NK + 8;
+  constexpr int KC = J / 16;                  // 32-K chunks of the SBD GEMM (K = 2J)
+  constexpr int SRT = 2 * J / 16;             // 16-row tiles of the SBD output (a, Re/Im)
+  constexpr int RT = (SRT + 7) / 8;           // SBD row tiles per wave
+  constexpr int JB = 16, JA = J / 16;         // segment-sum lanes: 16 per IF, J / 16 channels each
+  constexpr int NW = kBlockGemm / 64;
+  constexpr int YSUB = 16 * NK * YS, ASUB = J * AS;
+  constexpr int NU = J / 16;                    // 16-row units of the MBD GEMM per sub-grid
+  constexpr int CPU = 8;                        // cells per lane per unit
+  extern __shared__ float2 lds[];
+  __shared__ float red_v[NW];
+  __shared__ int32_t red_i[NW];
+
+  const int N = a.n_if, R = a.n_rate, P = a.sbd_pad;
+  const int PJ = P * J;
+  const int t = threadIdx.x, wave = t >> 6, lane = t & 63;
+
+  int dl, seg;
+  block_segment(a, DUMP, dl, seg);
+  int wi = 0;
+  while (wi + 1 < a.n_win && a.win_off[wi + 1] <= seg) ++wi;
+  const int l = a.win_len[wi];
+  const int q = seg - a.win_off[wi];
+  const int64_t k0 = a.win_k0[wi] + int64_t(q) * a.win_hop[wi];
+  const float2 *wd = a.w + int64_t(dl) * a.w_dm_stride + k0 * (N * J);
+  const float2 *rph = a.rate_ph + a.rate_off[wi];
+
+  int y_off, a_off, total;
+  gemm_lds_plan<J, NK>(P, y_off, a_off, total);
+  const int PB = gemm_batch<J, NK>(P);   // sub-grids per batch
+  float2 *TWs = lds;
+  _Float16 *Yl = reinterpret_cast<_Float16 *>(reinterpret_cast<char *>(lds) + y_off);
+  _Float16 *Am = reinterpret_cast<_Float16 *>(reinterpret_cast<char *>(lds) + a_off);
+  const float scale = a.mfma_scale;
+  for (int i = t; i < PJ; i += kBlockGemm) {
+    const float2 w = a.tw_sbd[i];
+    TWs[i] = make_float2(w.x * scale, w.y * scale);   // exact: scale is a power of two
+  }
+  // rows of IFs n >= N stay zero (K padding of the MBD GEMM, columns of the SBD GEMM)
+  for (int i = t; i < PB * YSUB; i += kBlockGemm) Yl[i] = _Float16(0.0f);
+
+  // constant operands, in registers for the kernel's life
+  h8_t fa[RT][KC];
+  {
+    const h8_t *src = static_cast<const h8_t *>(a.sbd_a);
+    static_for<0, RT>([&](auto kk) {
+      constexpr int k = decltype(kk)::value;
+      const int rt = wave + NW * k;
+      static_for<0, KC>([&](auto cc) {
+        constexpr int kc = decltype(cc)::value;
+        if (rt < SRT) fa[k][kc] = src[(rt * KC + kc) * 64 + lane];
+      });
+    });
+  }
+  h8_t bm[4][NK];   // MBD: Re tiles 2 wave + {0, 1}, Im tiles 16 + 2 wave + {0, 1}
+  {
+    const h8_t *src = static_cast<const h8_t *>(a.mfma_b_hi);
+    static_for<0, 4>([&](auto pp) {
+      constexpr int p = decltype(pp)::value;
+      const int tile = p < 2 ? 2 * wave + p : 16 + 2 * wave + (p - 2);
+      static_for<0, NK>([&](auto cc) {
+        constexpr int kc = decltype(cc)::value;
+        bm[p][kc] = src[(tile * NK + kc) * 64 + lane];
+      });
+    });
+  }
+
+  // segment-sum lanes: IF n1, channels j = 16 i + i2 (i < J / 16)
+  const bool s_act = t < N * JB;
+  const int n1 = t / JB, i2 = t % JB;
+  float2 y[JA];
+
+  // B operands of the SBD GEMM for sub-grids c0 .. c0 + nb - 1:
+  // w_PJ^{j c} scale Y(n, j) as float16
+  auto sbd_operands = [&](int c0, int nb) {
+    if (!s_act) return;
+    for (int cb = 0; cb < nb; ++cb) {
+      const int c = c0 + cb;
+      _Float16 *Y = Yl + cb * YSUB;
+      static_for<0, JA>([&](auto i) {
+        constexpr int ii = decltype(i)::value;
+        const int j = JB * ii + i2;
+        const float2 z = cmul(y[ii], TWs[j * c]);
+        h2_t h;
+        h.x = _Float16(z.x);
+        h.y = _Float16(z.y);
+        *reinterpret_cast<h2_t *>(Y + n1 * YS + 2 * j) = h;
+      });
+    }
+  };
+  // SBD GEMM of nb sub-grids: rows (a, Re/Im) of this wave's tiles, columns n
+  // -> float16 A rows of the MBD GEMM
+  auto sbd_gemm = [&](int nb) {
+    for (int cb = 0; cb < nb; ++cb) {
+      const _Float16 *Y = Yl + cb * YSUB;
+      _Float16 *A = Am + cb * ASUB;
+      static_for<0, RT>([&](auto kk) {
+        constexpr int k = decltype(kk)::value;
+        const int rt = wave + NW * k;
+        if (rt < SRT) {
+          static_for<0, NK>([&](auto ct) {
+            constexpr int cn = decltype(ct)::value;
+            h8_t bb[KC];
+            static_for<0, KC>([&](auto cc) {
+              constexpr int kc = decltype(cc)::value;
+              bb[kc] = *reinterpret_cast<const h8_t *>(Y + (16 * cn + (lane & 15)) * YS + 32 * kc +
+                                                       8 * (lane >> 4));
+            });
+            f4_t x = {0.f, 0.f, 0.f, 0.f};
+            static_for<0, KC>([&](auto cc) {
+              constexpr int kc = decltype(cc)::value;
+              x = __builtin_amdgcn_mfma_f32_16x16x32_f16(fa[k][kc], bb[kc], x, 0, 0, 0);
+            });
+            // rows 16 rt + 4 (lane / 16) + i: Re, Im of bins a0 and a0 + 1
+            const int n = 16 * cn + (lane & 15);
+            const int a0 = 8 * rt + 2 * (lane >> 4);
+            h2_t h0, h1;
+            h0.x = _Float16(x[0]);
+            h0.y = _Float16(x[1]);
+            h1.x = _Float16(x[2]);
+            h1.y = _Float16(x[3]);
+            *reinterpret_cast<h2_t *>(A + a0 * AS + 2 * n) = h0;
+            *reinterpret_cast<h2_t *>(A + (a0 + 1) * AS + 2 * n) = h1;
+          });
+        }
+      });
+    }
+  };
+  // MBD GEMM of the 16 SBD rows of unit u of sub-grid buffer cb: Re and Im
+  // of this wave's 32 MBD columns for the lane's CPU cells (slot 4 p + i:
+  // column tile p, accumulator row i)
+  auto mbd_unit = [&](int cb, int u, float (&gre)[CPU], float (&gim)[CPU]) {
+    const _Float16 *A = Am + cb * ASUB;
+    h8_t ah[NK];
+    const int arow = (16 * u + (lane & 15)) * AS + 8 * (lane >> 4);
+    static_for<0, NK>([&](auto cc) {
+      constexpr int kc = decltype(cc)::value;
+      ah[kc] = *reinterpret_cast<const h8_t *>(A + arow + 32 * kc);
+    });
+    static_for<0, 2>([&](auto pp) {
+      constexpr int p = decltype(pp)::value;
+      f4_t gr = {0.f, 0.f, 0.f, 0.f}, gi = {0.f, 0.f, 0.f, 0.f};
+      static_for<0, NK>([&](auto cc) {
+        constexpr int kc = decltype(cc)::value;
+        gr = __builtin_amdgcn_mfma_f32_16x16x32_f16(ah[kc], bm[p][kc], gr, 0, 0, 0);
+        gi = __builtin_amdgcn_mfma_f32_16x16x32_f16(ah[kc], bm[2 + p][kc], gi, 0, 0, 0);
+      });
+      static_for<0, 4>([&](auto ii) {
+        constexpr int q4 = decltype(ii)::value;
+        gre[4 * p + q4] = gr[q4];
+        gim[4 * p + q4] = gi[q4];
+      });
+    });
+  };
+  // packed index of cell `slot` of the lane in unit u of sub-grid c, rate r
+  auto cell_index = [&](int r, int c, int u, int slot) {
+    const int arow_i = 16 * u + 4 * (lane >> 4) + (slot & 3);
+    const int m = 16 * (2 * wave + (slot >> 2)) + (lane & 15);
+    const int s = (c + P * arow_i + (PJ >> 1)) & (PJ - 1);
+    return (r * PJ + s) * M + ((m + (M >> 1)) & (M - 1));
+  };
+
+  // ---- the search: per lane, the largest |G|^2 (as float bits: |G|^2 >= 0
+  // orders like its bits, and a NaN cell outranks every number and is then
+  // refused below) over each (rate, sub-grid), and the (rate, sub-grid) that
+  // holds it; the cell itself is found again at the end.
+  float best_v = -1.0f;
+  int best_rc = 0x7fffffff;
+  for (int r = 0; r < R; ++r) {
+    // Eq. 3 segment sum with the Eq. 4 rate rotation (j = 0 not fitted)
+    segment_sum<JA, JB>(y, wd, rph, r, N, J, l, R, s_act, n1, i2);
+    for (int c0 = 0; c0 < P; c0 += PB) {
+      sbd_operands(c0, PB);
+      __syncthreads();
+      sbd_gemm(PB);
+      __syncthreads();
+      for (int cb = 0; cb < PB; ++cb) {
+        const int c = c0 + cb;
+        unsigned m = 0u;
+        static_for<0, NU>([&](auto uu) {
+          constexpr int u = decltype(uu)::value;
+          float gre[CPU], gim[CPU];
+          mbd_unit(cb, u, gre, gim);
+          unsigned bits[CPU];
+          static_for<0, CPU>([&](auto e) {
+            constexpr int k = decltype(e)::value;
+            const float v = __builtin_fmaf(gim[k], gim[k], gre[k] * gre[k]);
+            bits[k] = __float_as_uint(v);
+            if constexpr (DUMP) a.dump[cell_index(r, c, u, k)] = v / (scale * scale);
+          });
+          static_for<0, CPU / 2>([&](auto e) {
+            constexpr int k = decltype(e)::value;
+            m = max(m, max(bits[2 * k], bits[2 * k + 1]));
+          });
+        });
+        const float bv = __uint_as_float(m);
+        if (bv > best_v) {
+          best_v = bv;
+          best_rc = r * P + c;
+        }
+      }
+    }
+  }
+  if constexpr (DUMP) return;
+
+  // ---- block maximum and its (rate, sub-grid): larger value, then lower
+  // (rate, sub-grid)
+  for (int off = 32; off > 0; off >>= 1) {
+    const float ov = __shfl_xor(best_v, off, 64);
+    const int orc = __shfl_xor(best_rc, off, 64);
+    if (ov > best_v || (ov == best_v && orc < best_rc)) {
+      best_v = ov;
+      best_rc = orc;
+    }
+  }
+  if (lane == 0) {
+    red_v[wave] = best_v;
+    red_i[wave] = best_rc;
+  }
+  __syncthreads();
+  float vmax = red_v[0];
+  int rc = red_i[0];
+  for (int w = 1; w < NW; ++w) {
+    if (red_v[w] > vmax || (red_v[w] == vmax && red_i[w] < rc)) {
+      vmax = red_v[w];
+      rc = red_i[w];
+    }
+  }
+  const int64_t o = int64_t(dl) * a.seg_total + seg;
+  if (!(vmax >= 0.0f)) {   // no finite cell (non-finite input)
+    if (t == 0) {
+      a.power[o] = __builtin_nanf("");
+      a.pidx[o] = -1;
+    }
+    return;
+  }
+  // ---- find the cell: the (rate, sub-grid) that holds the maximum is
+  // searched again with the same arithmetic, keeping the lowest packed
+  // index among the largest cells (keys: |G|^2 with the 4 lowest mantissa
+  // bits replaced by 15 - slot)
+  const int r = rc / P, c = rc % P;
+  segment_sum<JA, JB>(y, wd, rph, r, N, J, l, R, s_act, n1, i2);
+  __syncthreads();   // the red_* reads above are done before they are reused
+  sbd_operands(c, 1);
+  __syncthreads();
+  sbd_gemm(1);
+  __syncthreads();
+  float fv = -1.0f;
+  int32_t fi = 0x7fffffff;
+  static_for<0, NU>([&](auto uu) {
+    constexpr int u = decltype(uu)::value;
+    float gre[CPU], gim[CPU];
+    mbd_unit(0, u, gre, gim);
+    static_for<0, CPU>([&](auto e) {
+      constexpr int k = decltype(e)::value;
+      const float v = __builtin_fmaf(gim[k], gim[k], gre[k] * gre[k]);   // as in the scan
+      const int32_t ci = cell_index(r, c, u, k);
+      if (v > fv || (v == fv && ci < fi)) {
+        fv = v;
+        fi = ci;
+      }
+    });
+  });
+  for (int off = 32; off > 0; off >>= 1) {
+    const float ov = __shfl_xor(fv, off, 64);
+    const int32_t oi = __shfl_xor(fi, off, 64);
+    if (ov > fv || (ov == fv && oi < fi)) {
+      fv = ov;
+      fi = oi;
+    }
+  }
+  if (lane == 0) {
+    red_v[wave] = fv;
+    red_i[wave] = fi;
+  }
+  __syncthreads();
+  if (t == 0) {
+    float bv = red_v[0];
+    int32_t bi = red_i[0];
+    for (int w = 1; w < NW; ++w) {
+      if (red_v[w] > bv || (red_v[w] == bv && red_i[w] < bi)) {
+        bv = red_v[w];
+        bi = red_i[w];
+      }
+    }
+    a.power[o] = bv >= 0.0f ? sqrtf(bv) / scale : __builtin_nanf("");
+    a.pidx[o] = bv >= 0.0f ? bi : -1;
+  }
+}
+
 __global__ __launch_bounds__(kBlock) void cube_sum_kernel(const float *power, int64_t bl_stride,
                                                           const int32_t *bl, int n_bl, float *out,
                                                           int64_t n) {
@@ -1412,6 +1747,68 @@ bool fringe_mfma_supported(int n_chan, int n_mbd, int n_if, int sbd_pad, int n_p
   const int JB = n_chan >= 256 ? 16 : n_chan >= 64 ? 8 : 4;
   if (n_if * JB > kBlock) return false;
   const size_t b = fringe_mfma_lds_bytes(n_chan, n_if, sbd_pad, n_pass);
+  return b > 0 && b <= 150 * 1024;
+}
+
+template <int J, int NK>
+static hipError_t launch_gemm_t(const FringeArgs &a, size_t lds, int grid, hipStream_t s) {
+  (void)hipGetLastError();
+  auto go = [&](auto kern) -> hipError_t {
+    if (lds > 64 * 1024) {
+      const hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(kern),
+                                               hipFuncAttributeMaxDynamicSharedMemorySize, int(lds));
+      if (e != hipSuccess) return e;
+    }
+    hipLaunchKernelGGL(kern, dim3(grid), dim3(kBlockGemm), lds, s, a);
+    return hipGetLastError();
+  };
+  return a.dump ? go(&fringe_gemm_kernel<J, NK, true>) : go(&fringe_gemm_kernel<J, NK, false>);
+}
+
+template <int J>
+static hipError_t launch_gemm_j(int nk, const FringeArgs &a, size_t lds, int grid, hipStream_t s) {
+  if (nk == 1) return launch_gemm_t<J, 1>(a, lds, grid, s);
+  if (nk == 2) return launch_gemm_t<J, 2>(a, lds, grid, s);
+  return hipErrorInvalidValue;
+}
+
+hipError_t launch_fringe_gemm(int n_chan, int n_if, const FringeArgs &a, size_t lds, int grid,
+                              hipStream_t s) {
+  const int nk = mfma_nk(n_if);
+  if (!a.sbd_a || n_if * 16 > kBlockGemm) return hipErrorInvalidValue;
+  switch (n_chan) {
+    case 16: return launch_gemm_j<16>(nk, a, lds, grid, s);
+    case 32: return launch_gemm_j<32>(nk, a, lds, grid, s);
+    case 64: return launch_gemm_j<64>(nk, a, lds, grid, s);
+    case 128: return launch_gemm_j<128>(nk, a, lds, grid, s);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+size_t fringe_gemm_lds_bytes(int n_chan, int n_if, int sbd_pad) {
+  int yo, ao, tot;
+  const int nk = mfma_nk(n_if);
+  auto plan = [&](auto jc) {
+    constexpr int J = decltype(jc)::value;
+    if (nk == 1) gemm_lds_plan<J, 1>(sbd_pad, yo, ao, tot);
+    else gemm_lds_plan<J, 2>(sbd_pad, yo, ao, tot);
+  };
+  switch (n_chan) {
+    case 16: plan(std::integral_constant<int, 16>{}); break;
+    case 32: plan(std::integral_constant<int, 32>{}); break;
+    case 64: plan(std::integral_constant<int, 64>{}); break;
+    case 128: plan(std::integral_constant<int, 128>{}); break;
+    default: return 0;
+  }
+  return size_t(tot);
+}
+
+bool fringe_gemm_supported(int n_chan, int n_mbd, int n_if, int sbd_pad) {
+  if (n_mbd != 256 || mfma_nk(n_if) == 0) return false;
+  if (n_chan != 16 && n_chan != 32 && n_chan != 64 && n_chan != 128) return false;
+  // 16 segment-sum lanes per IF
+  if (n_if * 16 > kBlockGemm) return false;
+  const size_t b = fringe_gemm_lds_bytes(n_chan, n_if, sbd_pad);
   return b > 0 && b <= 150 * 1024;
 }
 

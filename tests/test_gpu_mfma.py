@@ -52,7 +52,7 @@ def test_f16x3_matches_oracle_at_float32_bar(J, N, R):
     compare_crossings(gpu["crossings"], ora["crossings"], 3.0)
 
 
-@pytest.mark.parametrize("J,N,R", [(64, 32, 2), (32, 8, 1)])
+@pytest.mark.parametrize("J,N,R", [(64, 32, 2), (32, 8, 1), (16, 12, 3), (128, 20, 1)])
 def test_f16_storage_and_products_within_1e3(J, N, R):
     wl = _wl(J, N, R, seed_id=95 + J, precision="f16")
     V, _ = W.generate(wl)
@@ -100,3 +100,32 @@ def test_f16x3_detections_equal_f32_path():
     assert rel.max() < 1e-4
     key = lambda d: (d["baseline"], d["dm_index"], d["k0"], d["window_len"])
     assert [key(d) for d in a["candidates"]] == [key(d) for d in b["candidates"]]
+
+
+@pytest.mark.parametrize("J,N", [(64, 32), (16, 12)])
+def test_f16_grid_dump_elementwise(J, N):
+    """Every cell of one segment's |G|^2 from the f16 form (SBD and MBD
+    transforms both on the matrix cores) against the oracle's grid on the
+    same stored complex32 values, relative to the grid maximum."""
+    import torch
+    from paper_1801_02391_amd import frbx
+    wl = _wl(J, N, 2, K=120, windows=(3, 8), n_dm=2, seed_id=97 + J, precision="f16")
+    V, _ = W.generate(wl)
+    H = W.to_complex32(V)
+    Vq = W.from_complex32(H)
+    g = O.build_grids(wl["layout"], wl["search"])
+    s = frbx.Search(wl["layout"])
+    s.configure(wl["search"])
+    s.load(torch.from_numpy(H).to("cuda:0"))
+    cal = np.ones((N, J))
+    worst = 0.0
+    for (d, wi, q) in [(0, 0, 0), (1, 1, g["segs"][1][2] - 1)]:
+        grid = s.dump_segment(0, d, wi, q)
+        l, h, _ = g["segs"][wi]
+        rph = O.rate_phasor(g["rates"], g["f0"], l, g["t_ap"])
+        Y = O.segment_sums(Vq[0], g["dk"][d], [q * h], l, rph, cal)
+        G = np.abs(O.fringe_matrix(Y, g["e_sbd"], g["e_mbd"])[0]) ** 2
+        err = np.abs(grid - G).max() / G.max()
+        worst = max(worst, err)
+        assert err < 2e-3
+    note(f"f16 grid dump J={J} N={N}: max |G|^2 error / max {worst:.2e}")
