@@ -281,23 +281,27 @@ def unpack_index(idx, n_sbd, n_mbd):
 # Normalisation and threshold (O9, O10)
 # ----------------------------------------------------------------------------
 def normalise(P):
-    """O9, Eq. 6: (|G| - mean) / std over the row, population std.
+    """O9, Eq. 6: (|G| - mean) / std over the row, population std.  A segment
+    whose power is not finite (its data hold a NaN or infinity) takes no part
+    in the statistics and has no normalised power (NaN), so it never crosses.
     Returns (P_norm or None when std == 0, mean, std)."""
     P = np.asarray(P, dtype=np.float64)
-    if P.size == 0:
+    ok = np.isfinite(P)
+    if not ok.any():
         return None, 0.0, 0.0
-    mu = P.mean()
-    sd = math.sqrt(((P - mu) ** 2).mean())
+    mu = P[ok].mean()
+    sd = math.sqrt(((P[ok] - mu) ** 2).mean())
     if sd == 0.0:
         return None, mu, sd
-    return (P - mu) / sd, mu, sd
+    return np.where(ok, (np.where(ok, P, mu) - mu) / sd, np.nan), mu, sd
 
 
 def crossings(P_norm, threshold):
-    """O10: segments whose normalised power is strictly above the threshold."""
+    """O10: segments whose normalised power is strictly above the threshold
+    (a NaN normalised power is not)."""
     if P_norm is None:
         return np.zeros(0, dtype=np.int64)
-    return np.nonzero(P_norm > threshold)[0]
+    return np.nonzero(np.nan_to_num(P_norm, nan=-np.inf) > threshold)[0]
 
 
 # ----------------------------------------------------------------------------

@@ -426,3 +426,70 @@ def test_power_summation_over_dm_trials():
     dets = O.power_sum_search(P, segs, 1.0, 3.0, 2, [0, 1])
     assert len(dets) == 1
     assert dets[0]["d"] == 1 and dets[0]["k0"] == 100 and dets[0]["n_windows"] == 2
+
+
+# ---------------------------------------------------------------- non-finite data
+def test_eq6_statistics_skip_non_finite_segments():
+    """Eq. 6 with missing data: the mean and population standard deviation of
+    a row are those of its finite powers alone (computed here with the
+    standard library), a non-finite power gets no normalised power and never
+    crosses, and the finite segments cross exactly as in the row without
+    the missing ones."""
+    import statistics
+    rng = np.random.default_rng(5)
+    P = rng.rayleigh(1.0, 400)
+    P[[7, 100]] = 9.0                       # two strong segments
+    bad = [3, 50, 51, 399]
+    Pm = P.copy()
+    Pm[bad[:2]] = np.nan
+    Pm[bad[2]] = np.inf
+    Pm[bad[3]] = -np.inf
+    pn, mu, sd = O.normalise(Pm)
+    fin = [float(x) for x in Pm if math.isfinite(x)]
+    assert mu == pytest.approx(statistics.fmean(fin), rel=1e-13)
+    assert sd == pytest.approx(statistics.pstdev(fin), rel=1e-12)
+    assert np.all(np.isnan(pn[bad]))
+    keep = np.setdiff1d(np.arange(400), bad)
+    pk, _, _ = O.normalise(P[keep])
+    assert np.allclose(pn[keep], pk, rtol=0, atol=1e-12)
+    cr = O.crossings(pn, 3.0)
+    assert not set(cr.tolist()) & set(bad)
+    assert cr.tolist() == keep[O.crossings(pk, 3.0)].tolist()
+    assert 7 in cr and 100 in cr
+    # a row with no finite power has no statistics and no crossings
+    pn0, mu0, sd0 = O.normalise(np.full(5, np.nan))
+    assert pn0 is None and O.crossings(pn0, 3.0).size == 0
+
+
+def test_nan_sample_makes_exactly_its_segments_non_finite():
+    """A NaN sample in channel (n, j) at AP k spoils exactly the segments
+    whose dedispersed frames include it (Eq. 3: AP k0 + dk_d(n, j) + u for
+    u < l), counted here by brute force over the segment list; every other
+    segment keeps its power, and a NaN in the DC point j = 0 (not fitted,
+    Sec. 2.3) spoils nothing."""
+    f0 = [3000.0, 3064.0]
+    J, K = 8, 60
+    lay = _layout(f0, J, 1.0, 1.0, K)
+    lay["n_baselines"] = 1
+    srch = _search(dm_lo=0.0, dm_step=300.0, n_dm=2, n_mbd=32, windows=[2, 4])
+    rng = np.random.default_rng(6)
+    V = (rng.standard_normal((1, 2, J, K)) + 1j * rng.standard_normal((1, 2, J, K))) / np.sqrt(2)
+    clean = O.search(V, lay, srch)
+    n, j, k = 1, 3, 20
+    Vn = V.copy()
+    Vn[0, n, j, k] = np.nan
+    res = O.search(Vn, lay, srch)
+    g = res["grids"]
+    for d in range(2):
+        for wi, (l, h, Q) in enumerate(g["segs"]):
+            P = res["cube"][(0, d, wi)][0]
+            dk = int(g["dk"][d][n][j])
+            hit = np.array([q * h + dk <= k <= q * h + dk + l - 1 for q in range(Q)])
+            assert hit.any()
+            assert np.array_equal(np.isnan(P), hit)
+            assert np.array_equal(P[~hit], clean["cube"][(0, d, wi)][0][~hit])
+    Vd = V.copy()
+    Vd[0, n, 0, k] = np.nan
+    res_dc = O.search(Vd, lay, srch)
+    for key, (P, _, _) in clean["cube"].items():
+        assert np.array_equal(res_dc["cube"][key][0], P)
