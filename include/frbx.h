@@ -161,6 +161,15 @@ frbx_status frbx_set_windows(frbx_ctx *ctx, const int32_t *len_frames, int32_t n
 frbx_status frbx_set_detection(frbx_ctx *ctx, double threshold, int32_t n_win_min,
                                int32_t n_bl_min);
 
+/* Device memory for the dedispersed DM tiles of frbx_run / frbx_stream_push,
+ * in bytes: the DM trials are dedispersed floor(bytes / tile) at a time, one
+ * trial's tile being (K - dk_max) x N x J x 8 bytes (K: the APs of the run or
+ * of the stream buffer).  0 (default) = 6 GiB, at least one trial per tile.
+ * A positive budget below one trial's tile makes the search fail with
+ * FRBX_E_NOMEM (the message gives both sizes); an allocation that the device
+ * refuses returns FRBX_E_NOMEM as well.  FRBX_E_INVAL for bytes < 0. */
+frbx_status frbx_set_tile_budget(frbx_ctx *ctx, int64_t bytes);
+
 /* Arithmetic of the fringe transform.
  *   FRBX_PREC_F32       float32 segment sums, SBD and MBD transforms on the
  *                       vector ALUs (in-register FFTs).  When every IF's MBD

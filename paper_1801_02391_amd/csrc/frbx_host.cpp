@@ -105,7 +105,8 @@ struct frbx_ctx {
   DevCrossing *d_cross = nullptr;
   unsigned long long *d_ncross = nullptr;
   int64_t cross_cap = 0;
-  size_t w_budget = size_t(6) << 30;
+  size_t w_budget = size_t(6) << 30;   // bytes for the dedispersed DM tiles
+  bool w_budget_strict = false;        // set by the caller: below one trial -> E_NOMEM
   // this device's copy of the no-alloc workspace (looked up at create)
   void *d_noalloc = nullptr;
   std::string noalloc_err;
@@ -953,6 +954,14 @@ frbx_status frbx_load_e4m3(frbx_ctx *c, const void *codes, const float *scale, i
   return finish_load(c, n_cplx, 0);
 }
 
+frbx_status frbx_set_tile_budget(frbx_ctx *c, int64_t bytes) {
+  if (!c) return FRBX_E_INVAL;
+  if (bytes < 0) return c->fail(FRBX_E_INVAL, "tile budget must be >= 0");
+  c->w_budget = bytes > 0 ? size_t(bytes) : (size_t(6) << 30);
+  c->w_budget_strict = bytes > 0;
+  return FRBX_OK;
+}
+
 frbx_status frbx_set_precision(frbx_ctx *c, int32_t precision) {
   if (!c) return FRBX_E_INVAL;
   if (precision != FRBX_PREC_F32 && precision != FRBX_PREC_F16X3 && precision != FRBX_PREC_F16)
@@ -1185,6 +1194,9 @@ frbx_status device_pass(frbx_ctx *c, const PassSpec &ps, std::vector<DevCrossing
   const int64_t S = ps.S;
   const int64_t k_eff = ps.K - c->dk_max;
   const size_t per_dm = size_t(std::max<int64_t>(k_eff, 0)) * NJ;
+  if (c->w_budget_strict && per_dm * sizeof(float2) > c->w_budget)
+    return c->fail(FRBX_E_NOMEM, "tile budget of " + std::to_string(c->w_budget) + " bytes is below one DM trial's " +
+                                     "dedispersed tile (" + std::to_string(per_dm * sizeof(float2)) + " bytes)");
   c->dt = per_dm ? int(std::max<size_t>(1, std::min<size_t>(D, c->w_budget / (per_dm * sizeof(float2))))) : 1;
   while (c->dt > 1 && int64_t(c->dt) * S > (int64_t(1) << 31) - 1) c->dt /= 2;
   if ((s = ensure(c, c->d_w, c->w_cap, per_dm * c->dt)) != FRBX_OK) return s;

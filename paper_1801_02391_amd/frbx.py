@@ -72,6 +72,7 @@ _SIGS = {
     "frbx_load": ([_P, _P, C.c_int], C.c_int),
     "frbx_load_f16": ([_P, _P, C.c_int], C.c_int),
     "frbx_set_precision": ([_P, C.c_int32], C.c_int),
+    "frbx_set_tile_budget": ([_P, C.c_int64], C.c_int),
     "frbx_run": ([_P], C.c_int),
     "frbx_run_cube_noalloc": ([_P, _P, _P, C.c_int64, C.POINTER(C.c_int64)], C.c_int),
     "frbx_get_segments": ([_P, _P, _P, _P, _P], C.c_int),
@@ -315,6 +316,10 @@ class Search:
 
     def run(self):
         self._chk(lib().frbx_run(self._h), "run")
+
+    def set_tile_budget(self, n_bytes):
+        """Device memory for the dedispersed DM tiles (0: default 6 GiB)."""
+        self._chk(lib().frbx_set_tile_budget(self._h, int(n_bytes)), "set_tile_budget")
 
     def run_cube_noalloc(self, power, idx):
         """frbx_run_cube_noalloc into caller-owned contiguous GPU tensors
