@@ -32,7 +32,7 @@ PEAK_FP16_MFMA_TFLOPS = 2500.0  # MI355X dense FP16 matrix, published
 PEAK_HBM_GBS = 8000.0        # MI355X HBM3E, published
 # channel counts for which the f16 form runs its SBD transform on the matrix
 # cores as well (the library's fringe_gemm_kernel)
-SBD_GEMM_CHANNELS = (16, 32, 64, 128)
+SBD_GEMM_CHANNELS = (16, 32, 64)
 
 
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_vgos_6bl_20000.txt")
@@ -422,7 +422,7 @@ def run_form(args, wl, V, prec, dev, truth, budget, reserve_after, headline):
         # the method's matrix-core work: the real-embedded MBD GEMM, 2 x (2N)
         # x (2M) flops per SBD bin, i.e. 8 N flops per cell; f16x3 issues it
         # three times (high/low split), reported separately.  The f16 form
-        # also runs the SBD transform as a real-embedded GEMM where J <= 128:
+        # also runs the SBD transform as a real-embedded GEMM where J <= 64:
         # per (segment, rate) P sub-grids of 2 x (2J) x (2J) x N flops over
         # PJ M cells, 8 N J / M flops per cell.
         fpc = 8 * N

@@ -184,10 +184,10 @@ frbx_status frbx_set_tile_budget(frbx_ctx *ctx, int64_t bytes);
  *                       accumulation): products good to ~2^-21 relative.
  *   FRBX_PREC_F16       one float16 product (inputs and DFT matrices
  *                       rounded once to float16, float32 accumulation), and
- *                       for n_chan <= 128 the SBD transform on the matrix
+ *                       for n_chan <= 64 the SBD transform on the matrix
  *                       cores too: per SBD sub-grid a real-embedded J-point
  *                       DFT of the rotated segment sums (float32 segment
- *                       sums, float16 operands); for n_chan = 256 the SBD
+ *                       sums, float16 operands); for n_chan >= 128 the SBD
  *                       transform runs as in FRBX_PREC_F16X3.
  * The matrix-core forms need n_mbd = 256, n_chan >= 16 and n_if <= 32
  * (FRBX_E_INVAL at frbx_run otherwise); their operands are scaled by a

@@ -1,8 +1,10 @@
 // Internal interface between the host side of libfrbx and its HIP kernels.
 #pragma once
 
+#ifndef __HIPCC_RTC__
 #include <hip/hip_runtime.h>
 #include <stdint.h>
+#endif
 
 namespace frbx {
 
@@ -116,6 +118,7 @@ struct StatsArgs {
   int64_t cap;
 };
 
+#ifndef __HIPCC_RTC__
 // Launch wrappers (defined in frbx_kernels.hip).  They return the HIP status
 // of the launch.
 hipError_t launch_dedisperse(const DedisperseArgs &a, hipStream_t s);
@@ -220,5 +223,6 @@ hipError_t launch_absmax(const void *vis, int64_t n, int in_f16, unsigned int *o
 constexpr size_t kNoAllocBytes = size_t(64) << 20;
 constexpr int kMaxDevices = 64;
 hipError_t noalloc_workspace(int device, void **ptr);
+#endif  // !__HIPCC_RTC__
 
 }  // namespace frbx
