@@ -79,8 +79,12 @@ def mbd_one_pass_rows(s, M):
     return {16: 4, 32: 4, 64: 8, 128: 8, 256: 16}[M]
 
 
-def mbd_form(rows):
+def mbd_form(rows, s=None):
     if not rows:
+        spec = s.specialisation()[0] if s is not None else 0
+        if spec:
+            return {"mbd_form": f"two-pass, first pass on {bin(spec).count('1')} rows "
+                                f"(row set {spec:#x}, kernel compiled for the IF lattice)"}
         return {"mbd_form": "two-pass"}
     return {"mbd_form": f"one-pass (compact IF lattice, {rows} rows)",
             "note": "achieved counts the work of the one-pass form (the first MBD pass is skipped)"}
@@ -448,7 +452,7 @@ def run_form(args, wl, V, prec, dev, truth, budget, reserve_after, headline):
             "kernel": kern, "avg_launch_ms": round(avg_ms, 4),
             "flops_per_cell": round(fpc, 3), "units_per_launch": units_per_launch}
     if prec == "f32":
-        roof.update(mbd_form(rows))
+        roof.update(mbd_form(rows, s))
     # dedispersion kernel against HBM: every dedispersed spectrum written
     # once and every channel's input span read once per group of DM trials
     # (byte count reported by the library per launch)
@@ -598,7 +602,7 @@ def run_stream(args):
         "roofline": {"bound": bound, "achieved": round(ach, 3), "peak": peak, "unit": "TFLOP/s",
                      "frac": round(ach / peak, 4), "traffic": None, "kernel": kern,
                      "avg_launch_ms": round(avg, 4), "flops_per_cell": round(fpc, 2),
-                     "units_per_launch": units, **(mbd_form(s) if args.precision == "f32" else {})},
+                     "units_per_launch": units, **(mbd_form(mbd_one_pass_rows(s, M), s) if args.precision == "f32" else {})},
         "quantisation": quant,
     }
 

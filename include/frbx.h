@@ -198,6 +198,24 @@ typedef enum { FRBX_PREC_F32 = 0, FRBX_PREC_F16X3 = 1, FRBX_PREC_F16 = 2 } frbx_
 
 frbx_status frbx_set_precision(frbx_ctx *ctx, int32_t precision);
 
+/* Kernel specialisation (not a step of the paper).  In FRBX_PREC_F32,
+ * when the IF lattice of Eq. 5 is not compact (the general form of the
+ * fringe kernel), the kernel is compiled at run time (hipRTC, gfx950, about
+ * 2 s once per process, device, n_chan, n_mbd and row set) for the rows of
+ * its first MBD pass that hold an IF, which that pass then alone reads and
+ * transforms.  It computes the same sums as the statically built kernel;
+ * as a separate compilation its multiply-add fusion may differ, so powers
+ * agree to float32 rounding (a few parts in 10^6).  enable = 0 keeps the
+ * statically built kernel; default 1.  Takes effect at the next frbx_run. */
+frbx_status frbx_set_specialisation(frbx_ctx *ctx, int enable);
+
+/* The row set of the kernel the last frbx_run used (bit i1 for lattice
+ * positions (n_mbd / A) i1 + i2, A the first pass's row count); 0 for the
+ * statically built kernel.  *why (may be NULL) receives the reason the
+ * specialised kernel could not be built, or "" (valid until the next
+ * frbx_run on this context). */
+frbx_status frbx_get_specialisation(const frbx_ctx *ctx, uint32_t *rows, const char **why);
+
 /* Float32 re-evaluation of the crossings of the matrix-core forms (not a
  * step of the paper; it gives their threshold decisions and crossing peaks
  * float32 arithmetic).  With band > 0, after the search in FRBX_PREC_F16X3
@@ -206,6 +224,11 @@ frbx_status frbx_set_precision(frbx_ctx *ctx, int32_t precision);
  * float32 kernel (its segment sums gathered straight from the input with
  * the AP offsets), its power and index are replaced in the cube, and the
  * statistics, crossings and detections are taken from the updated cube.
+ * That cube keeps the matrix-core powers of every segment outside the
+ * band, so the Eq. 6 mean and deviation, and with them every normalised
+ * power, differ from a float32 search's by about the form's power error
+ * (up to 2.3e-3 in P_norm measured on the precision workload): crossings
+ * that close to the threshold can still differ.
  * band = 0 (default) turns it off; ignored in FRBX_PREC_F32; FRBX_E_INVAL
  * for band < 0.  Its launch is not among the kernel times of
  * frbx_get_timing (the run's wall time includes it). */

@@ -11,18 +11,22 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
-#include <type_traits>
-
 #include "frbx_internal.h"
 #endif
 
 namespace frbx {
 
 // ---------------------------------------------------------------- helpers
+// A compile-time loop index (value usable in constant expressions).
+template <int I>
+struct Index {
+  static constexpr int value = I;
+};
+
 template <int I, int N, typename F>
 __device__ __forceinline__ void static_for(F &&f) {
   if constexpr (I < N) {
-    f(std::integral_constant<int, I>{});
+    f(Index<I>{});
     static_for<I + 1, N>(f);
   }
 }
@@ -110,6 +114,67 @@ __device__ __forceinline__ void dft(float2 (&x)[NP]) {
       const float2 a = x[i0], c = x[i1];
       x[i0] = cadd(a, c);
       x[i1] = twmul<pos * (NP / (2 * span)), NP>(csub(a, c));
+    });
+  });
+  float2 y[NP];
+  static_for<0, NP>([&](auto i) {
+    constexpr int ii = decltype(i)::value;
+    y[bitrev(ii, L)] = x[ii];
+  });
+  static_for<0, NP>([&](auto i) { x[decltype(i)::value] = y[decltype(i)::value]; });
+}
+
+// Inputs of the radix-2 decimation-in-frequency DFT below that can be non-
+// zero before stage `stage`, given those of the input (bit i: x[i]): a
+// butterfly's two outputs are zero exactly when both its inputs are.
+constexpr unsigned dft_stage_mask(int np, unsigned mask, int stage) {
+  for (int st = 0; st < stage; ++st) {
+    const int span = np >> (st + 1);
+    unsigned out = 0u;
+    for (int b = 0; b < np / 2; ++b) {
+      const int grp = b / span, pos = b % span;
+      const int i0 = grp * 2 * span + pos, i1 = i0 + span;
+      if (((mask >> i0) | (mask >> i1)) & 1u) out |= (1u << i0) | (1u << i1);
+    }
+    mask = out;
+  }
+  return mask;
+}
+
+// dft<NP> for an input that is zero outside the compile-time set MASK (bit
+// i: x[i] may be non-zero; the others must hold +0): butterflies with two
+// zero inputs are skipped and those with one skip the addition.  The
+// results equal dft<NP>'s (adding an exact zero changes nothing but, at
+// most, the sign of a zero).
+template <int NP, unsigned MASK>
+__device__ __forceinline__ void dft_masked(float2 (&x)[NP]) {
+  constexpr int L = ilog2(NP);
+  static_for<0, L>([&](auto st) {
+    constexpr int stage = decltype(st)::value;
+    constexpr unsigned nz = dft_stage_mask(NP, MASK, stage);
+    constexpr int span = NP >> (stage + 1);
+    static_for<0, NP / 2>([&](auto bi) {
+      constexpr int b = decltype(bi)::value;
+      constexpr int grp = b / span, pos = b % span;
+      constexpr int i0 = grp * 2 * span + pos, i1 = i0 + span;
+      constexpr bool z0 = !((nz >> i0) & 1u), z1 = !((nz >> i1) & 1u);
+      constexpr int tk = pos * (NP / (2 * span));
+      if constexpr (z0 && z1) {
+        // both zero: so are both outputs
+      } else if constexpr (z1) {
+        x[i1] = twmul<tk, NP>(x[i0]);
+      } else if constexpr (z0) {
+        // x[i0] holds an exact +0: 0 - c, as in dft<NP>, keeps the product
+        // and its rounding the same as the dense transform's (the compiler
+        // may not fold it into a negation)
+        const float2 c = x[i1];
+        x[i1] = twmul<tk, NP>(csub(x[i0], c));
+        x[i0] = c;
+      } else {
+        const float2 a = x[i0], c = x[i1];
+        x[i0] = cadd(a, c);
+        x[i1] = twmul<tk, NP>(csub(a, c));
+      }
     });
   });
   float2 y[NP];
@@ -318,10 +383,15 @@ __device__ __forceinline__ void mbd_column_peak(const float2 (&z)[MB], int r, in
 // and transforms; the first pass and its LDS transpose drop out.
 // LIST: one work-group per entry of a.seg_list instead of per segment of the
 // tile (re-evaluation of selected segments).
-template <int J, int M, bool DUMP, bool CL, bool LIST = false>
+// ROWS (general form): the rows i1 of the first MBD pass that hold an IF
+// (bit i1 for lattice positions MB i1 + i2), 0 for all; the pass then
+// reads and transforms only those rows (a kernel specialised to the IF
+// lattice when the search starts; the same sums).
+template <int J, int M, bool DUMP, bool CL, bool LIST = false, unsigned ROWS = 0u>
 __global__ __launch_bounds__(kBlock) void fringe_kernel(FringeArgs a) {
   using S = FringeShape<J, M>;
   constexpr int JA = S::JA, JB = S::JB, MA = S::MA, MB = S::MB, G = S::G, COLS = S::COLS;
+  constexpr unsigned RMASK = ROWS ? ROWS : (MA >= 32 ? ~0u : (1u << MA) - 1u);
   extern __shared__ float2 lds[];
   __shared__ float red_v[kBlock / 64];
   __shared__ int32_t red_i[kBlock / 64];
@@ -385,7 +455,7 @@ __global__ __launch_bounds__(kBlock) void fringe_kernel(FringeArgs a) {
     static_for<0, MA>([&](auto k) {
       constexpr int kk = decltype(k)::value;
       twm[kk] = a.tw_mbd[(gl * kk) & (M - 1)];
-      rowoff[kk] = a.mbd_row[MB * kk + gl] * XS;
+      if constexpr ((RMASK >> kk) & 1u) rowoff[kk] = a.mbd_row[MB * kk + gl] * XS;
     });
   }
   float2 *Sg = Sc + grp * S::SG;
@@ -452,9 +522,10 @@ __global__ __launch_bounds__(kBlock) void fringe_kernel(FringeArgs a) {
               float2 x[MA];
               static_for<0, MA>([&](auto i) {
                 constexpr int ii = decltype(i)::value;
-                x[ii] = X[rowoff[ii] + col];
+                if constexpr ((RMASK >> ii) & 1u) x[ii] = X[rowoff[ii] + col];
+                else x[ii] = make_float2(0.f, 0.f);
               });
-              dft<MA>(x);
+              dft_masked<MA, RMASK>(x);
               static_for<0, MA>([&](auto k) {
                 constexpr int kk = decltype(k)::value;
                 Sg[kk * MB + (gl ^ (kk & (MB - 1)))] = cmul(x[kk], twm[kk]);

@@ -77,6 +77,10 @@ struct frbx_ctx {
   int32_t *d_list = nullptr;     // their (DM trial, segment) list
   size_t list_cap = 0;
   int32_t mbd_shift = -1;        // that shift, -1 for the general form
+  int specialise = 1;            // float32 general form: kernel compiled for the lattice's rows
+  unsigned rows_mask = 0;        // rows of the kernel in use (0: the statically built kernel)
+  hipFunction_t rows_fn = nullptr;
+  std::string rows_note;         // why the specialised kernel is not in use
   std::vector<int> rate_off;
   int dd_group = 1;          // DM trials per staged dedispersion tile
 
@@ -363,7 +367,7 @@ float2 cis_cycles(double x) {
 }
 
 // The float16 form runs both transforms on the matrix cores where the
-// shape allows (n_chan <= 128); otherwise its SBD stays on the vector ALUs.
+// shape allows (n_chan <= 64); otherwise its SBD stays on the vector ALUs.
 bool use_gemm(const frbx_ctx *c) {
   return c->precision == FRBX_PREC_F16 && frbx::fringe_gemm_supported(c->J, c->n_mbd, c->N, c->sbd_pad);
 }
@@ -509,22 +513,44 @@ frbx_status prepare(frbx_ctx *c) {
     // K-chunk kc is row 32 kc + 8 (l / 16) + e, column 16 t + l % 16.
     const int NK = N <= 16 ? 1 : 2;
     std::vector<_Float16> bh(size_t(32) * NK * 64 * 8), bl(bh.size());
-    for (int t = 0; t < 32; ++t)
-      for (int kc = 0; kc < NK; ++kc)
-        for (int ln = 0; ln < 64; ++ln)
-          for (int e = 0; e < 8; ++e) {
-            const int k = 32 * kc + 8 * (ln / 16) + e, n = k / 2, comp = k % 2;
-            const int m = 16 * (t % 16) + ln % 16;
-            double v = 0.0;
-            if (n < N) {
-              const double th = kTwoPi * double((c->q_if[n] * m) % M) / M;
-              const double cs = std::cos(th), sn = std::sin(th);
-              v = t < 16 ? (comp == 0 ? cs : sn) : (comp == 0 ? -sn : cs);
+    if (frbx::mfma_three_real(J, N, n_pass)) {
+      // Three-real-product form: for tile t < 16 (columns m in [16 t,
+      // 16 t + 16)) the matrices c = cos, d = -sin and c + d of the
+      // twiddle w_M^(q_n m), K = n < 32 (zero for n >= N), in the same
+      // per-lane order: lane ln, element e is row 8 (ln / 16) + e.
+      for (int t = 0; t < 16; ++t)
+        for (int mat = 0; mat < 3; ++mat)
+          for (int ln = 0; ln < 64; ++ln)
+            for (int e = 0; e < 8; ++e) {
+              const int n = 8 * (ln / 16) + e, m = 16 * t + ln % 16;
+              double v = 0.0;
+              if (n < N) {
+                const double th = kTwoPi * double((c->q_if[n] * m) % M) / M;
+                const double cs = std::cos(th), dd = -std::sin(th);
+                v = mat == 0 ? cs : mat == 1 ? dd : cs + dd;
+              }
+              const size_t o = ((size_t(t) * 3 + mat) * 64 + ln) * 8 + e;
+              bh[o] = static_cast<_Float16>(v);
+              bl[o] = static_cast<_Float16>(v - double(bh[o]));
             }
-            const size_t o = ((size_t(t) * NK + kc) * 64 + ln) * 8 + e;
-            bh[o] = static_cast<_Float16>(v);
-            bl[o] = static_cast<_Float16>(v - double(bh[o]));
-          }
+    } else {
+      for (int t = 0; t < 32; ++t)
+        for (int kc = 0; kc < NK; ++kc)
+          for (int ln = 0; ln < 64; ++ln)
+            for (int e = 0; e < 8; ++e) {
+              const int k = 32 * kc + 8 * (ln / 16) + e, n = k / 2, comp = k % 2;
+              const int m = 16 * (t % 16) + ln % 16;
+              double v = 0.0;
+              if (n < N) {
+                const double th = kTwoPi * double((c->q_if[n] * m) % M) / M;
+                const double cs = std::cos(th), sn = std::sin(th);
+                v = t < 16 ? (comp == 0 ? cs : sn) : (comp == 0 ? -sn : cs);
+              }
+              const size_t o = ((size_t(t) * NK + kc) * 64 + ln) * 8 + e;
+              bh[o] = static_cast<_Float16>(v);
+              bl[o] = static_cast<_Float16>(v - double(bh[o]));
+            }
+    }
     if ((s = up(c->d_mfma_hi, bh)) != FRBX_OK) return s;
     if ((s = up(c->d_mfma_lo, bl)) != FRBX_OK) return s;
     if (use_gemm(c)) {
@@ -548,6 +574,24 @@ frbx_status prepare(frbx_ctx *c) {
               fa[((size_t(rt) * KC + kc) * 64 + ln) * 8 + e] = static_cast<_Float16>(v);
             }
       if ((s = up(c->d_sbd_a, fa)) != FRBX_OK) return s;
+    }
+  }
+  // Float32 general form: the fringe kernel compiled for the rows of the
+  // first MBD pass that hold an IF (the same sums, only those rows read
+  // and transformed); the statically built kernel when every row holds an
+  // IF or the run-time compiler cannot build it.
+  c->rows_fn = nullptr;
+  c->rows_mask = 0;
+  c->rows_note.clear();
+  const int MB = frbx::fringe_compact_rows(M);
+  if (c->specialise && c->precision == FRBX_PREC_F32 && c->mbd_pos.empty() && MB > 0) {
+    const int MA = M / MB;
+    unsigned rows = 0;
+    for (int n = 0; n < N; ++n) rows |= 1u << (c->q_if[n] / MB);
+    const unsigned all = MA >= 32 ? ~0u : (1u << MA) - 1u;
+    if (rows != all) {
+      c->rows_fn = frbx::fringe_rows_kernel(c->device, J, M, rows, &c->rows_note);
+      if (c->rows_fn) c->rows_mask = rows;
     }
   }
   c->dirty = false;
@@ -972,6 +1016,20 @@ frbx_status frbx_set_precision(frbx_ctx *c, int32_t precision) {
   return FRBX_OK;
 }
 
+frbx_status frbx_set_specialisation(frbx_ctx *c, int enable) {
+  if (!c) return FRBX_E_INVAL;
+  c->specialise = enable ? 1 : 0;
+  c->dirty = true;
+  return FRBX_OK;
+}
+
+frbx_status frbx_get_specialisation(const frbx_ctx *c, uint32_t *rows, const char **why) {
+  if (!c) return FRBX_E_INVAL;
+  if (rows) *rows = c->rows_mask;
+  if (why) *why = c->rows_note.c_str();
+  return FRBX_OK;
+}
+
 frbx_status frbx_set_recheck(frbx_ctx *c, double band) {
   if (!c) return FRBX_E_INVAL;
   if (!(band >= 0.0)) return c->fail(FRBX_E_INVAL, "recheck band must be >= 0");
@@ -1178,8 +1236,10 @@ frbx_status search_tiles(frbx_ctx *c, const PassSpec &ps, float2 *wbuf, int dt, 
         fa.mfma_b_lo = c->d_mfma_lo;
         fa.mfma_scale = scale;
         sp = c->span_begin(0, int64_t(ndt) * S);
-        const hipError_t le = use_mfma ? launch_matrix_core(c, fa, int(ndt * S))
-                                       : frbx::launch_fringe(J, M, fa, lds, int(ndt * S), c->stream);
+        const hipError_t le =
+            use_mfma    ? launch_matrix_core(c, fa, int(ndt * S))
+            : c->rows_fn ? frbx::launch_fringe_rows(c->rows_fn, fa, lds, int(ndt * S), c->stream)
+                         : frbx::launch_fringe(J, M, fa, lds, int(ndt * S), c->stream);
         if ((s = c->hip(le, "fringe launch")) != FRBX_OK) return s;
         c->span_end(sp);
       }

@@ -4,6 +4,14 @@
 #ifndef __HIPCC_RTC__
 #include <hip/hip_runtime.h>
 #include <stdint.h>
+
+#include <string>
+#else
+// hipRTC declares the fixed-width integers in a namespace of its own
+using __hip_internal::int32_t;
+using __hip_internal::int64_t;
+using __hip_internal::uint32_t;
+using __hip_internal::uint64_t;
 #endif
 
 namespace frbx {
@@ -137,6 +145,13 @@ hipError_t launch_stats(const StatsArgs &a, int rows, hipStream_t s);
 // matrix-core fringe kernel: n_pass = 1 (float16) or 3 (float16 high/low
 // split, float32-grade products); supports n_mbd = 256, n_chan >= 16,
 // n_if <= 32
+// The 3-pass matrix-core form with 17-32 IFs and at most 64 channels forms
+// each complex product of the MBD GEMM from three real products; its B
+// table holds, per tile of 16 MBD columns, the matrices cos, -sin and
+// cos - sin (K = IF).
+constexpr bool mfma_three_real(int n_chan, int n_if, int n_pass) {
+  return n_pass == 3 && n_if > 16 && n_if <= 32 && n_chan <= 64;
+}
 hipError_t launch_fringe_mfma(int n_chan, int n_if, int n_pass, const FringeArgs &a,
                               size_t lds_bytes, int grid, hipStream_t s);
 size_t fringe_mfma_lds_bytes(int n_chan, int n_if, int sbd_pad, int n_pass);
@@ -223,6 +238,16 @@ hipError_t launch_absmax(const void *vis, int64_t n, int in_f16, unsigned int *o
 constexpr size_t kNoAllocBytes = size_t(64) << 20;
 constexpr int kMaxDevices = 64;
 hipError_t noalloc_workspace(int device, void **ptr);
+
+// The float32 fringe kernel of the general MBD form specialised to the
+// rows of its first MBD pass that hold an IF (bit i1 of `rows`), compiled
+// at run time with hipRTC for the current device (defined in
+// frbx_jit.cpp).  The first call for a (device, n_chan, n_mbd, rows)
+// compiles and loads it; later calls return the loaded function.  nullptr
+// with the reason in *err when it cannot be built.
+hipFunction_t fringe_rows_kernel(int device, int n_chan, int n_mbd, unsigned rows, std::string *err);
+hipError_t launch_fringe_rows(hipFunction_t fn, const FringeArgs &a, size_t lds_bytes, int grid,
+                              hipStream_t s);
 #endif  // !__HIPCC_RTC__
 
 }  // namespace frbx

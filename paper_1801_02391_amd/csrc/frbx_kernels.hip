@@ -216,6 +216,12 @@ __global__ __launch_bounds__(kBlock) void stats_kernel(StatsArgs a) {
 // 3-pass form, its residual to a second float16) and staged in LDS in the
 // A-operand layout.  Each of the 4 waves owns 64 MBD columns and keeps
 // their B operands in registers for the kernel's life.
+// With 17-32 IFs and at most 64 channels (where the larger A tiles still
+// leave room for three work-groups per CU) the 3-pass form builds each
+// complex product from three real ones (X W with W = c + i d: P1 = Re X c, P2 = Im X d, P3 = (Re X +
+// Im X)(c + d); Re = P1 - P2, Im = P3 - P1 - P2): three GEMMs of K = 32
+// over the IFs (A chunks Re X, Im X, Re X + Im X; B matrices c, d, c + d)
+// in place of two of K = 64, a quarter fewer matrix-core instructions.
 typedef _Float16 h8_t __attribute__((ext_vector_type(8)));
 typedef _Float16 h2_t __attribute__((ext_vector_type(2)));
 typedef float f4_t __attribute__((ext_vector_type(4)));
@@ -224,7 +230,7 @@ template <int J, int NK>
 __host__ __device__ inline void mfma_lds_plan(int n_if, int sbd_pad, int n_pass, int &t_off,
                                               int &a_off, int &total_bytes) {
   constexpr int JA = Split<J>::A, JB = Split<J>::B;
-  constexpr int AS = 32 * NK + 8;
+  const int AS = 32 * (mfma_three_real(J, 16 * NK, n_pass) ? 3 : NK) + 8;
   const int t_bytes = n_if * JA * (JB + 1) * 8;
   const int tw_bytes = sbd_pad * J * 8;
   t_off = t_bytes;                               // TW after the transpose scratch
@@ -232,11 +238,16 @@ __host__ __device__ inline void mfma_lds_plan(int n_if, int sbd_pad, int n_pass,
   total_bytes = a_off + (n_pass == 3 ? 2 : 1) * J * AS * 2;
 }
 
+// The three-product form runs three waves per SIMD (168 VGPRs, no spill).
 template <int J, int NK, int NP, bool DUMP>
-__global__ __launch_bounds__(kBlock) void fringe_mfma_kernel(FringeArgs a) {
+__global__ __launch_bounds__(kBlock)
+__attribute__((amdgpu_waves_per_eu(mfma_three_real(J, 16 * NK, NP) && !DUMP ? 3 : 1)))
+void fringe_mfma_kernel(FringeArgs a) {
   constexpr int M = 256;
   constexpr int JA = Split<J>::A, JB = Split<J>::B;
-  constexpr int AS = 32 * NK + 8;   // A row stride in halves (+16 B against bank conflicts)
+  constexpr bool K3 = mfma_three_real(J, 16 * NK, NP);  // three real products per complex one
+  constexpr int NKA = K3 ? 3 : NK;          // A chunks of 32 per row
+  constexpr int AS = 32 * NKA + 8;  // A row stride in halves (+16 B against bank conflicts)
   constexpr int NSB = J / 16;       // 16-row SBD blocks per tile
   extern __shared__ float2 lds[];
   __shared__ float red_v[kBlock / 64];
@@ -267,18 +278,20 @@ __global__ __launch_bounds__(kBlock) void fringe_mfma_kernel(FringeArgs a) {
   for (int i = t; i < PJ; i += kBlock) TW[i] = a.tw_sbd[i];
   for (int i = t; i < (NP == 3 ? 2 : 1) * J * AS; i += kBlock) Ahi[i] = _Float16(0.0f);
 
-  // B operands of this wave: Re tiles 4 wave + p and Im tiles 16 + 4 wave + p
-  h8_t bh[8][NK], bl[8][NK];
+  // B operands of this wave: Re tiles 4 wave + p and Im tiles 16 + 4 wave + p;
+  // K3: matrices c, d, c + d of tile 4 wave + p
+  constexpr int NBT = K3 ? 4 : 8, NBK = K3 ? 3 : NK;
+  h8_t bh[NBT][NBK], bl[NBT][NBK];
   {
     const h8_t *srch = static_cast<const h8_t *>(a.mfma_b_hi);
     const h8_t *srcl = static_cast<const h8_t *>(a.mfma_b_lo);
-    static_for<0, 8>([&](auto qq) {
+    static_for<0, NBT>([&](auto qq) {
       constexpr int p8 = decltype(qq)::value;
-      const int tile = p8 < 4 ? 4 * wave + p8 : 16 + 4 * wave + (p8 - 4);
-      static_for<0, NK>([&](auto kk) {
+      const int tile = K3 ? 4 * wave + p8 : (p8 < 4 ? 4 * wave + p8 : 16 + 4 * wave + (p8 - 4));
+      static_for<0, NBK>([&](auto kk) {
         constexpr int kc = decltype(kk)::value;
-        bh[p8][kc] = srch[(tile * NK + kc) * 64 + lane];
-        if constexpr (NP == 3) bl[p8][kc] = srcl[(tile * NK + kc) * 64 + lane];
+        bh[p8][kc] = srch[(tile * NBK + kc) * 64 + lane];
+        if constexpr (NP == 3) bl[p8][kc] = srcl[(tile * NBK + kc) * 64 + lane];
       });
     });
   }
@@ -311,25 +324,38 @@ __global__ __launch_bounds__(kBlock) void fringe_mfma_kernel(FringeArgs a) {
         static_for<0, JB>([&](auto k) {
           constexpr int kk = decltype(k)::value;
           const float xr = z[kk].x * scale, xi = z[kk].y * scale;
-          h2_t hi;
-          hi.x = _Float16(xr);
-          hi.y = _Float16(xi);
-          const int o = (k1 + JA * kk) * AS + 2 * n2;
-          *reinterpret_cast<h2_t *>(Ahi + o) = hi;
-          if constexpr (NP == 3) {
-            h2_t lo;
-            lo.x = _Float16(xr - float(hi.x));
-            lo.y = _Float16(xi - float(hi.y));
-            *reinterpret_cast<h2_t *>(Alo + o) = lo;
+          if constexpr (K3) {
+            // chunks Re X, Im X, Re X + Im X at K = n
+            const int o = (k1 + JA * kk) * AS + n2;
+            const float xs = xr + xi;
+            const _Float16 hr = _Float16(xr), hi_ = _Float16(xi), hs = _Float16(xs);
+            Ahi[o] = hr;
+            Ahi[o + 32] = hi_;
+            Ahi[o + 64] = hs;
+            Alo[o] = _Float16(xr - float(hr));
+            Alo[o + 32] = _Float16(xi - float(hi_));
+            Alo[o + 64] = _Float16(xs - float(hs));
+          } else {
+            h2_t hi;
+            hi.x = _Float16(xr);
+            hi.y = _Float16(xi);
+            const int o = (k1 + JA * kk) * AS + 2 * n2;
+            *reinterpret_cast<h2_t *>(Ahi + o) = hi;
+            if constexpr (NP == 3) {
+              h2_t lo;
+              lo.x = _Float16(xr - float(hi.x));
+              lo.y = _Float16(xi - float(hi.y));
+              *reinterpret_cast<h2_t *>(Alo + o) = lo;
+            }
           }
         });
       }
       __syncthreads();
       // MBD on the matrix cores, 16 SBD rows at a time
       for (int sb = 0; sb < NSB; ++sb) {
-        h8_t ah[NK], al[NK];
+        h8_t ah[NKA], al[NKA];
         const int arow = (16 * sb + (lane & 15)) * AS + 8 * (lane >> 4);
-        static_for<0, NK>([&](auto kk) {
+        static_for<0, NKA>([&](auto kk) {
           constexpr int kc = decltype(kk)::value;
           ah[kc] = *reinterpret_cast<const h8_t *>(Ahi + arow + 32 * kc);
           if constexpr (NP == 3) al[kc] = *reinterpret_cast<const h8_t *>(Alo + arow + 32 * kc);
@@ -341,17 +367,38 @@ __global__ __launch_bounds__(kBlock) void fringe_mfma_kernel(FringeArgs a) {
         static_for<0, 4>([&](auto pp) {
           constexpr int p = decltype(pp)::value;
           f4_t gr = {0.f, 0.f, 0.f, 0.f}, gi = {0.f, 0.f, 0.f, 0.f};
-          static_for<0, NK>([&](auto kk) {
-            constexpr int kc = decltype(kk)::value;
-            if constexpr (NP == 3) {
-              gr = __builtin_amdgcn_mfma_f32_16x16x32_f16(al[kc], bh[p][kc], gr, 0, 0, 0);
-              gi = __builtin_amdgcn_mfma_f32_16x16x32_f16(al[kc], bh[4 + p][kc], gi, 0, 0, 0);
-              gr = __builtin_amdgcn_mfma_f32_16x16x32_f16(ah[kc], bl[p][kc], gr, 0, 0, 0);
-              gi = __builtin_amdgcn_mfma_f32_16x16x32_f16(ah[kc], bl[4 + p][kc], gi, 0, 0, 0);
-            }
-            gr = __builtin_amdgcn_mfma_f32_16x16x32_f16(ah[kc], bh[p][kc], gr, 0, 0, 0);
-            gi = __builtin_amdgcn_mfma_f32_16x16x32_f16(ah[kc], bh[4 + p][kc], gi, 0, 0, 0);
-          });
+          if constexpr (K3) {
+            f4_t p3 = {0.f, 0.f, 0.f, 0.f};
+            // small products first, as below
+            gr = __builtin_amdgcn_mfma_f32_16x16x32_f16(al[0], bh[p][0], gr, 0, 0, 0);
+            gi = __builtin_amdgcn_mfma_f32_16x16x32_f16(al[1], bh[p][1], gi, 0, 0, 0);
+            p3 = __builtin_amdgcn_mfma_f32_16x16x32_f16(al[2], bh[p][2], p3, 0, 0, 0);
+            gr = __builtin_amdgcn_mfma_f32_16x16x32_f16(ah[0], bl[p][0], gr, 0, 0, 0);
+            gi = __builtin_amdgcn_mfma_f32_16x16x32_f16(ah[1], bl[p][1], gi, 0, 0, 0);
+            p3 = __builtin_amdgcn_mfma_f32_16x16x32_f16(ah[2], bl[p][2], p3, 0, 0, 0);
+            gr = __builtin_amdgcn_mfma_f32_16x16x32_f16(ah[0], bh[p][0], gr, 0, 0, 0);
+            gi = __builtin_amdgcn_mfma_f32_16x16x32_f16(ah[1], bh[p][1], gi, 0, 0, 0);
+            p3 = __builtin_amdgcn_mfma_f32_16x16x32_f16(ah[2], bh[p][2], p3, 0, 0, 0);
+            // gr = P1, gi = P2 -> Re, Im
+            static_for<0, 4>([&](auto ii) {
+              constexpr int i = decltype(ii)::value;
+              const float p1 = gr[i], p2 = gi[i];
+              gr[i] = p1 - p2;
+              gi[i] = (p3[i] - p1) - p2;
+            });
+          } else {
+            static_for<0, NK>([&](auto kk) {
+              constexpr int kc = decltype(kk)::value;
+              if constexpr (NP == 3) {
+                gr = __builtin_amdgcn_mfma_f32_16x16x32_f16(al[kc], bh[p][kc], gr, 0, 0, 0);
+                gi = __builtin_amdgcn_mfma_f32_16x16x32_f16(al[kc], bh[4 + p][kc], gi, 0, 0, 0);
+                gr = __builtin_amdgcn_mfma_f32_16x16x32_f16(ah[kc], bl[p][kc], gr, 0, 0, 0);
+                gi = __builtin_amdgcn_mfma_f32_16x16x32_f16(ah[kc], bl[4 + p][kc], gi, 0, 0, 0);
+              }
+              gr = __builtin_amdgcn_mfma_f32_16x16x32_f16(ah[kc], bh[p][kc], gr, 0, 0, 0);
+              gi = __builtin_amdgcn_mfma_f32_16x16x32_f16(ah[kc], bh[4 + p][kc], gi, 0, 0, 0);
+            });
+          }
           static_for<0, 4>([&](auto ii) {
             constexpr int i = decltype(ii)::value;
             const float v = gr[i] * gr[i] + gi[i] * gi[i];

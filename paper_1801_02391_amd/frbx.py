@@ -73,6 +73,8 @@ _SIGS = {
     "frbx_load_f16": ([_P, _P, C.c_int], C.c_int),
     "frbx_set_precision": ([_P, C.c_int32], C.c_int),
     "frbx_set_tile_budget": ([_P, C.c_int64], C.c_int),
+    "frbx_set_specialisation": ([_P, C.c_int], C.c_int),
+    "frbx_get_specialisation": ([_P, C.POINTER(C.c_uint32), C.POINTER(C.c_char_p)], C.c_int),
     "frbx_run": ([_P], C.c_int),
     "frbx_run_cube_noalloc": ([_P, _P, _P, C.c_int64, C.POINTER(C.c_int64)], C.c_int),
     "frbx_get_segments": ([_P, _P, _P, _P, _P], C.c_int),
@@ -320,6 +322,19 @@ class Search:
     def set_tile_budget(self, n_bytes):
         """Device memory for the dedispersed DM tiles (0: default 6 GiB)."""
         self._chk(lib().frbx_set_tile_budget(self._h, int(n_bytes)), "set_tile_budget")
+
+    def set_specialisation(self, enable):
+        """frbx_set_specialisation: float32 fringe kernel compiled for the
+        IF lattice's first-pass rows (True, default) or the static one."""
+        self._chk(lib().frbx_set_specialisation(self._h, 1 if enable else 0), "set_specialisation")
+
+    def specialisation(self):
+        """(row mask of the kernel the last run used, 0 for the static
+        kernel; reason it could not be built, or '')."""
+        rows = C.c_uint32(0)
+        why = C.c_char_p()
+        self._chk(lib().frbx_get_specialisation(self._h, C.byref(rows), C.byref(why)), "get_specialisation")
+        return int(rows.value), (why.value or b"").decode()
 
     def run_cube_noalloc(self, power, idx):
         """frbx_run_cube_noalloc into caller-owned contiguous GPU tensors

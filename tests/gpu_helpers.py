@@ -81,3 +81,127 @@ def compare_crossings(gpu_cross, ora_cross, thr):
     for k in set(g) & set(o):
         assert abs(g[k]["power_norm"] - o[k]["p_norm"]) <= 1e-3, k
     return n_marg
+
+
+def _steps_bd(cs, idx, t_amb, n_win_min):
+    """Sec. 2.4.1 steps b-d over the crossings cs[i], i in idx (one baseline
+    and DM trial), as the oracle takes them; per group: members, extent,
+    MBD-filter distances, survivors and the detection (k0, l) or None."""
+    order = sorted(idx, key=lambda i: (-cs[i]["l"], cs[i]["k0"], i))
+    groups = []
+    for i in order:
+        O._insert(groups, i, cs[i]["k0"], cs[i]["k0"] + cs[i]["l"] - 1)
+    out = []
+    for g in groups:
+        mem = [i for (i, _, _) in g]
+        mbar = O.circular_mean([cs[i]["mbd_us"] for i in mem], t_amb)
+        dist = [abs(O.wrapped_diff(cs[i]["mbd_us"], mbar, t_amb)) for i in mem]
+        surv = [i for i, x in zip(mem, dist) if x < t_amb / 4.0]
+        det = None
+        if surv and len({cs[i]["l"] for i in surv}) >= n_win_min:
+            best = max(surv, key=lambda i: cs[i]["p_norm"])
+            det = (cs[best]["k0"], cs[best]["l"], cs[best]["p_norm"])
+        out.append(dict(mem=mem, lo=min(x for (_, x, _) in g), hi=max(x for (_, _, x) in g),
+                        dist=dist, surv=surv, det=det))
+    return out
+
+
+def marginal_regions(cross, t_amb, thr, n_win_min, eps=MARGINAL, reasons=None):
+    """Time intervals, per baseline, whose single-pulse decisions (Sec. 2.4.1
+    steps b-d, the best-DM merge of Sec. 5.3) could go either way within the
+    tolerance of the search, tol = eps max(1, thr) in normalised power.
+
+    A detection of steps b-d (one baseline and DM trial) is marginal when
+      * dropping its group's marginal crossings (|P_norm - thr| <= tol)
+        changes what the steps make of the group,
+      * a member's MBD-filter distance lies within eps t_amb of T/4, or
+      * its best survivor leads the runner-up by <= tol (its k0 and l could
+        be the runner-up's).
+    A best-DM group (the detections of one pulse over the DM trials) is
+    marginal, and its extent a marginal region, when its best detection
+    leads the runner-up by <= tol, when that best detection is marginal, or
+    when dropping its marginal detections changes the group's outcome.
+    cross: dicts with b, d, l, k0, p_norm, mbd_us (the oracle's keys).
+    Returns {b: [(k_lo, k_hi), ...]}; `reasons` (a list) receives
+    (b, k_lo, k_hi, what) for every marginal best-DM group."""
+    tol = eps * max(1.0, thr)
+
+    def tie(vals):
+        v = sorted(vals, reverse=True)
+        return len(v) > 1 and v[0] - v[1] <= tol
+
+    by_bd = {}
+    for c in cross:
+        by_bd.setdefault((c["b"], c["d"]), []).append(c)
+    per_b = {}
+    for (b, d), cs in sorted(by_bd.items()):
+        for g in _steps_bd(cs, range(len(cs)), t_amb, n_win_min):
+            why = []
+            near = [i for i in g["mem"] if abs(cs[i]["p_norm"] - thr) <= tol]
+            if near:
+                rest = [i for i in g["mem"] if i not in near]
+                alt = [h["det"][:2] for h in _steps_bd(cs, rest, t_amb, n_win_min) if h["det"]]
+                if alt != ([g["det"][:2]] if g["det"] else []):
+                    why.append("threshold")
+            if any(abs(x - t_amb / 4.0) <= eps * t_amb for x in g["dist"]):
+                why.append("mbd-filter")
+            if g["det"] and tie([cs[i]["p_norm"] for i in g["surv"]]):
+                why.append("best-crossing tie")
+            if g["det"] or why:
+                # a marginal group without a detection here may give one on
+                # the other side: it takes part as a marginal member
+                k0, l, pn = g["det"] if g["det"] else (g["lo"], g["hi"] - g["lo"] + 1, -1.0)
+                per_b.setdefault(b, []).append(dict(d=d, k0=k0, l=l, p_norm=pn, why=why,
+                                                    real=g["det"] is not None))
+
+    def merge(dets, idx):
+        order = sorted(idx, key=lambda i: (dets[i]["d"], dets[i]["k0"], i))
+        groups = []
+        for i in order:
+            O._insert(groups, i, dets[i]["k0"], dets[i]["k0"] + dets[i]["l"] - 1)
+        return [[i for (i, _, _) in g] for g in groups]
+
+    def outcome(dets, groups):
+        out = []
+        for mem in groups:
+            real = [i for i in mem if dets[i]["real"]]
+            if real:
+                best = max(real, key=lambda i: dets[i]["p_norm"])
+                out.append((dets[best]["d"], dets[best]["k0"], dets[best]["l"]))
+        return sorted(out)
+
+    regions = {}
+    for b, dets in per_b.items():
+        for mem in merge(dets, range(len(dets))):
+            real = [i for i in mem if dets[i]["real"]]
+            what = None
+            if tie([dets[i]["p_norm"] for i in real]):
+                what = "best-DM tie"
+            elif real and dets[max(real, key=lambda i: dets[i]["p_norm"])]["why"]:
+                what = "best detection marginal"
+            else:
+                marg = [i for i in mem if dets[i]["why"]]
+                if marg:
+                    rest = [i for i in mem if i not in marg]
+                    if outcome(dets, merge(dets, rest)) != outcome(dets, [mem]):
+                        what = "marginal member changes the merge"
+            if what:
+                lo = min(dets[i]["k0"] for i in mem)
+                hi = max(dets[i]["k0"] + dets[i]["l"] - 1 for i in mem)
+                regions.setdefault(b, []).append((lo, hi))
+                if reasons is not None:
+                    reasons.append((b, lo, hi, what))
+    return regions
+
+
+def compare_detections(dets_a, dets_b, regions):
+    """Single-pulse lists (dicts with b, d, l, k0) identical outside the
+    marginal regions (union of both sides'); returns the number of
+    detections set aside as marginal."""
+    def inside(x):
+        return any(lo <= x["k0"] + x["l"] - 1 and x["k0"] <= hi for (lo, hi) in regions.get(x["b"], ()))
+    key = lambda x: (x["b"], x["d"], x["l"], x["k0"])
+    a = {key(x) for x in dets_a if not inside(x)}
+    bb = {key(x) for x in dets_b if not inside(x)}
+    assert a == bb, f"non-marginal detections differ: {sorted(a - bb)[:8]} vs {sorted(bb - a)[:8]}"
+    return sum(1 for x in dets_a if inside(x)) + sum(1 for x in dets_b if inside(x))

@@ -10,6 +10,8 @@ import subprocess
 
 import pytest
 
+from paper_1801_02391_amd.build import write_rtc_source
+
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 CSRC = os.path.join(ROOT, "paper_1801_02391_amd", "csrc")
 INC = os.path.join(ROOT, "include")
@@ -27,7 +29,7 @@ pytestmark = pytest.mark.skipif(not (os.path.exists(HIPCC) and os.path.exists(CL
 
 def _digest():
     h = hashlib.sha256()
-    for name in ("frbx_host.cpp", "frbx_kernels.hip", "frbx_internal.h"):
+    for name in ("frbx_host.cpp", "frbx_kernels.hip", "frbx_internal.h", "frbx_fringe.h", "frbx_jit.cpp"):
         h.update(open(os.path.join(CSRC, name), "rb").read())
     h.update(open(os.path.join(INC, "frbx.h"), "rb").read())
     h.update(" ".join(SAN_HOST).encode())
@@ -44,12 +46,16 @@ def san_lib():
                  "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops"]
         k = os.path.join(out, "k.o")
         h = os.path.join(out, "h.o")
+        j = os.path.join(out, "j.o")
+        write_rtc_source()
+        subprocess.run([HIPCC, "-c", *flags, *SAN_HOST, os.path.join(CSRC, "frbx_jit.cpp"), "-o", j],
+                       check=True, capture_output=True)
         subprocess.run([HIPCC, "-c", *flags, *SAN_HOST, os.path.join(CSRC, "frbx_kernels.hip"), "-o", k],
                        check=True, capture_output=True)
         subprocess.run([HIPCC, "-c", *flags, "-ffp-contract=off", *SAN_HOST,
                         os.path.join(CSRC, "frbx_host.cpp"), "-o", h], check=True, capture_output=True)
         tmp = lib + ".tmp"
-        subprocess.run([HIPCC, "-shared", "--offload-arch=gfx950", "-fPIC", k, h, "-o", tmp],
+        subprocess.run([HIPCC, "-shared", "--offload-arch=gfx950", "-fPIC", k, h, j, "-lhiprtc", "-o", tmp],
                        check=True, capture_output=True)
         os.replace(tmp, lib)
     return out
