@@ -120,7 +120,31 @@ class Budget:
         return self.deadline - time.perf_counter()
 
 
-def fringe_flops_per_cell(N, J, P, M, one_pass_rows=0):
+# rows of the first MBD pass of the float32 kernel per lattice size
+MBD_PASS1_ROWS = {16: 4, 32: 8, 64: 8, 128: 16, 256: 16}
+
+
+def pruned_dft_flops(n, mask):
+    """Work of an n-point radix-2 decimation-in-frequency DFT whose inputs
+    outside `mask` (bit i: input i may be non-zero) are zero, counted as the
+    kernel does it: a butterfly with two non-zero inputs 10 flops (the
+    5 n log2 n convention), with one non-zero input 6 (its twiddle product
+    only), with none 0."""
+    flops, span = 0, n // 2
+    while span >= 1:
+        out = 0
+        for b in range(n // 2):
+            i0 = (b // span) * 2 * span + b % span
+            i1 = i0 + span
+            nz = ((mask >> i0) & 1) + ((mask >> i1) & 1)
+            flops += (0, 6, 10)[nz]
+            if nz:
+                out |= (1 << i0) | (1 << i1)
+        mask, span = out, span // 2
+    return flops
+
+
+def fringe_flops_per_cell(N, J, P, M, one_pass_rows=0, first_pass_rows=0):
     """Algorithmic FP32 work per evaluated cell of the FFT-form search: per
     (segment, rate) an SBD transform per IF (N * 5 PJ log2 PJ), an MBD
     transform per SBD bin (PJ * 5 M log2 M), |G|^2 and compare (4 PJ M) and
@@ -129,15 +153,30 @@ def fringe_flops_per_cell(N, J, P, M, one_pass_rows=0):
     one_pass_rows = MB > 0 counts the one-pass MBD form of a compact IF
     lattice instead, the work that form does: per SBD bin, M / MB lanes
     each twiddle MB - 1 rows (6 flops each) and run one MB-point transform
-    (5 MB log2 MB)."""
+    (5 MB log2 MB).  first_pass_rows (a row set, bit i1) counts the
+    two-pass form whose first pass transforms only those rows: the MBD
+    term scaled by the pruned pass's share of the two passes' butterflies."""
     PJ = P * J
     if one_pass_rows:
         MB = one_pass_rows
         mbd = PJ * (M // MB) * (6 * (MB - 1) + 5 * MB * math.log2(MB))
     else:
         mbd = PJ * 5 * M * math.log2(M)
+        if first_pass_rows:
+            MA = MBD_PASS1_ROWS[M]
+            MB = M // MA
+            dense1 = MB * pruned_dft_flops(MA, (1 << MA) - 1)
+            pass2 = MA * pruned_dft_flops(MB, (1 << MB) - 1)
+            mbd *= (MB * pruned_dft_flops(MA, first_pass_rows) + pass2) / (dense1 + pass2)
     per = N * 5 * PJ * math.log2(PJ) + mbd + 4 * PJ * M + 8 * N * J
     return per / (PJ * M)
+
+
+def three_real_products(form, N, J):
+    """Whether the matrix-core MBD GEMM of this form forms each complex
+    product from three real ones (the library's rule: f16x3 with 17-32 IFs
+    and at most 64 channels)."""
+    return form == "f16x3" and 16 < N <= 32 and J <= 64
 
 
 def cpu_baseline(wl, V, target_s=15.0):
@@ -419,20 +458,28 @@ def run_form(args, wl, V, prec, dev, truth, budget, reserve_after, headline):
     extra = {}
     if prec == "f32":
         # FFT-form FP32 work on the vector ALUs (the one-pass form's own work
-        # when it runs)
-        fpc = fringe_flops_per_cell(N, J, P, M, rows)
+        # when it runs, the pruned first pass's when the kernel is compiled
+        # for the lattice's rows)
+        spec_rows = s.specialisation()[0] if not rows else 0
+        fpc = fringe_flops_per_cell(N, J, P, M, rows, spec_rows)
         bound, peak, kern = "alu", PEAK_FP32_TFLOPS, "fringe_kernel"
     else:
-        # the method's matrix-core work: the real-embedded MBD GEMM, 2 x (2N)
-        # x (2M) flops per SBD bin, i.e. 8 N flops per cell; f16x3 issues it
-        # three times (high/low split), reported separately.  The f16 form
-        # also runs the SBD transform as a real-embedded GEMM where J <= 64:
-        # per (segment, rate) P sub-grids of 2 x (2J) x (2J) x N flops over
-        # PJ M cells, 8 N J / M flops per cell.
-        fpc = 8 * N
+        # the matrix-core work: the real-embedded MBD GEMM, 2 x (2N) x (2M)
+        # flops per SBD bin, i.e. 8 N flops per cell, or 6 N where each
+        # complex product is formed from three real ones (three GEMMs of
+        # K = N); f16x3 issues it three times (high/low split), reported
+        # separately.  The f16 form also runs the SBD transform as a
+        # real-embedded GEMM where J <= 64: per (segment, rate) P sub-grids
+        # of 2 x (2J) x (2J) x N flops over PJ M cells, 8 N J / M flops per
+        # cell.
+        k3 = three_real_products(base_prec, N, J)
+        fpc = (6 if k3 else 8) * N
+        extra["mbd_products"] = "three real per complex" if k3 else "four real per complex"
+        extra["method_flops_per_cell"] = 8 * N
         kern = "fringe_mfma_kernel"
         if base_prec == "f16" and J in SBD_GEMM_CHANNELS:
             fpc += 8 * N * J / M
+            extra["method_flops_per_cell"] += 8 * N * J / M
             kern = "fringe_gemm_kernel"
         bound, peak = "mfma", PEAK_FP16_MFMA_TFLOPS
     flops_launch = units_per_launch * cells_per_unit * fpc
@@ -441,8 +488,8 @@ def run_form(args, wl, V, prec, dev, truth, budget, reserve_after, headline):
         extra = {"attainable_peak_unpacked": PEAK_FP32_UNPACKED_TFLOPS,
                  "frac_attainable": round(achieved / PEAK_FP32_UNPACKED_TFLOPS, 4)}
     elif base_prec == "f16x3":
-        extra = {"issued_products": 3, "achieved_issued": round(3 * achieved, 3),
-                 "frac_issued": round(3 * achieved / peak, 4)}
+        extra.update({"issued_products": 3, "achieved_issued": round(3 * achieved, 3),
+                      "frac_issued": round(3 * achieved / peak, 4)})
     tkey = kern if prec == "f32" else f"{kern}_{base_prec}"
     traffic = measured_traffic(tkey, args.workload)
     roof = {"bound": bound, "achieved": round(achieved, 3), "peak": peak,
@@ -576,10 +623,15 @@ def run_stream(args):
     avg = tim["fringe_ms"] / max(1, tim["n_fringe"])
     units = tim["fringe_units"] / max(1, tim["n_fringe"])
     if args.precision == "f32":
-        fpc, bound, peak, kern = fringe_flops_per_cell(N, J, P, M), "alu", PEAK_FP32_TFLOPS, "fringe_kernel"
+        rows = mbd_one_pass_rows(s, M)
+        fpc = fringe_flops_per_cell(N, J, P, M, rows, 0 if rows else s.specialisation()[0])
+        bound, peak, kern = "alu", PEAK_FP32_TFLOPS, "fringe_kernel"
     else:
-        fpc = 8 * N * (3 if args.precision == "f16x3" else 1)
+        fpc = (6 if three_real_products(args.precision, N, J) else 8) * N * (3 if args.precision == "f16x3" else 1)
         bound, peak, kern = "mfma", PEAK_FP16_MFMA_TFLOPS, "fringe_mfma_kernel"
+        if args.precision == "f16" and J in SBD_GEMM_CHANNELS:
+            fpc += 8 * N * J / M
+            kern = "fringe_gemm_kernel"
     ach = units * cells_seg * fpc / (avg * 1e-3) / 1e12 if avg > 0 else 0.0
     d_avg = tim["dedisperse_ms"] / max(1, tim["n_dedisperse"])
     d_gbs = tim["dedisperse_bytes"] / max(1, tim["n_dedisperse"]) / (d_avg * 1e-3) / 1e9 if d_avg > 0 else 0.0

@@ -76,3 +76,21 @@ def test_algorithmic_flops_per_cell_of_the_one_pass_form():
     assert bench.fringe_flops_per_cell(8, 32, 4, 256, 16) == 1008640 / 32768 == 30.78125
     # below the two-pass count of the same shape
     assert bench.fringe_flops_per_cell(8, 32, 4, 256) > 30.78125
+
+
+def test_work_of_the_pruned_first_pass():
+    """Hand count for the VGOS row set {0, 4, 6, 7, 14} of a 16-point
+    decimation-in-frequency transform: stage 1 (span 8) has three butterflies
+    with one non-zero input and one with two (3 x 6 + 10 = 28), stage 2
+    four with two and four with one (44), stage 3 four and four (64), stage
+    4 eight full butterflies (80): 216 of the dense 5 x 16 x 4 = 320."""
+    sys.path.insert(0, ROOT)
+    import bench
+    assert bench.pruned_dft_flops(16, 0xFFFF) == 320
+    assert bench.pruned_dft_flops(16, 0x40D1) == 28 + 44 + 64 + 80
+    assert bench.pruned_dft_flops(16, 0x0001) == 6 * (8 + 4 + 2 + 1) - 6 * 0
+    # two-pass VGOS cell: 16 lanes x (216 instead of 320) in the first pass,
+    # 16 x 320 in the second, of 5 x 256 x 8 = 10240 FFT-form flops
+    full = bench.fringe_flops_per_cell(32, 64, 4, 256)
+    pruned = bench.fringe_flops_per_cell(32, 64, 4, 256, 0, 0x40D1)
+    assert abs((full - pruned) * 65536 - 256 * 10240 * (1 - (16 * 216 + 16 * 320) / (32 * 320))) < 1e-6
