@@ -36,18 +36,21 @@ SBD_GEMM_CHANNELS = (16, 32, 64)
 
 
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_vgos_6bl_20000.txt")
-KERNEL_SOURCE = os.path.join(ROOT, "paper_1801_02391_amd", "csrc", "frbx_kernels.hip")
+KERNEL_SOURCES = [os.path.join(ROOT, "paper_1801_02391_amd", "csrc", f)
+                  for f in ("frbx_kernels.hip", "frbx_fringe.h")]
 
 
 def kernel_code_sha256():
-    """SHA-256 of the kernel source without its // comments and blank lines:
-    a change of code (not of commentary) invalidates measured counters."""
+    """SHA-256 of the kernel sources without their // comments and blank
+    lines: a change of code (not of commentary) invalidates measured
+    counters."""
     import hashlib
     lines = []
-    for line in open(KERNEL_SOURCE):
-        code = line.split("//", 1)[0].rstrip()
-        if code:
-            lines.append(code)
+    for path in KERNEL_SOURCES:
+        for line in open(path):
+            code = line.split("//", 1)[0].rstrip()
+            if code:
+                lines.append(code)
     return hashlib.sha256("\n".join(lines).encode()).hexdigest()
 
 

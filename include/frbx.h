@@ -25,7 +25,10 @@
  *   build the grid tables on the device after a grid changed
  *   (frbx_get_segments, frbx_get_lattice, frbx_get_ap_offsets,
  *   frbx_refine_cells); it is reused across calls and freed by
- *   frbx_destroy.  frbx_run_cube_noalloc allocates nothing (it runs in a
+ *   frbx_destroy.  The table builders also load, once per process, device
+ *   and lattice, the run-time compiled float32 kernel (see
+ *   frbx_set_specialisation), whose code stays loaded until the process
+ *   ends.  frbx_run_cube_noalloc allocates nothing (it runs in a
  *   fixed per-GPU workspace).  No entry point frees memory the caller owns.
  */
 #ifndef FRBX_H

@@ -571,54 +571,6 @@ class Search:
                                               self._dev(h, torch.float64, (n, 6))), "refine_curvature")
         return h
 
-    def refine_autograd(self, peaks, steps=20, max_step=0.5):
-        """The library's ascent driven through the torch.autograd.Function:
-        each step evaluates P (forward kernel), back-propagates P.sum()
-        (backward kernel), takes the curvature (curvature kernel) and applies
-        the same trust-region Newton update as frbx_refine_run.  Returns
-        (theta0, theta, P)."""
-        torch = self._torch
-        th0 = self.refine_begin(peaks)
-        n = len(peaks)
-        cells_np, xbar = self.refine_cells()
-        dev = f"cuda:{self.device}"
-        cells = torch.tensor(cells_np, dtype=torch.float64, device=dev)
-        a = -xbar * cells_np[3] / cells_np[4] if cells_np[4] > 0 else 0.0
-        live = cells > 0
-        theta = torch.tensor(th0, dtype=torch.float64, device=dev).requires_grad_(True)
-        best_t = theta.detach().clone()
-        best_s = torch.zeros((n, 5), dtype=torch.float64, device=dev)
-        best_p = torch.full((n,), -1.0, dtype=torch.float32, device=dev)
-        rad = torch.full((n,), float(max_step), dtype=torch.float64, device=dev)
-        for _ in range(steps):
-            P = refine_power(theta, self)
-            P.sum().backward()
-            with torch.no_grad():
-                g = theta.grad
-                H = self.refine_curvature(theta.detach().contiguous())
-                gz = g * cells
-                gz[:, 3] += a * g[:, 4] * cells[4]
-                hz = H[:, :5] * cells * cells
-                hz[:, 3] += 2 * a * H[:, 5] * cells[3] * cells[4] + a * a * H[:, 4] * cells[4] ** 2
-                newton = -gz / torch.where(hz < 0, hz, -torch.ones_like(hz))
-                st = torch.where(hz < 0, newton, max_step * torch.sign(gz)).clamp(-max_step, max_step)
-                st = torch.where(live, st, torch.zeros_like(st))
-                acc = P.detach() >= best_p
-                best_s = torch.where(acc[:, None], st, best_s)
-                best_t = torch.where(acc[:, None], theta.detach(), best_t)
-                best_p = torch.where(acc, P.detach(), best_p)
-                rad = torch.where(acc, torch.clamp(2 * rad, max=max_step), 0.5 * rad)
-                d = torch.maximum(torch.minimum(best_s, rad[:, None]), -rad[:, None])
-                d[:, 4] += a * d[:, 3]
-                theta.copy_(best_t + cells * d)
-            theta.grad = None
-        with torch.no_grad():
-            P = self.refine_forward(theta.detach().contiguous())
-            worse = P < best_p
-            theta_f = torch.where(worse[:, None], best_t, theta.detach())
-            P = torch.where(worse, best_p, P)
-        return th0, theta_f.cpu().numpy(), P.cpu().numpy()
-
     def set_timing(self, enable=True):
         self._chk(lib().frbx_set_timing(self._h, int(bool(enable))), "set_timing")
 
