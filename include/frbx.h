@@ -316,7 +316,12 @@ frbx_status frbx_get_ap_offsets(const frbx_ctx *ctx, int32_t *out, int64_t cap, 
 /* Power cube: power[b][d][seg] = max |G| of the segment and idx = packed
  * (r * PJ + s) * M + m of its lowest-index maximum; seg runs over the windows
  * in order, each window's segments consecutive.  Host buffers, cap in
- * elements; either pointer may be NULL. */
+ * elements; either pointer may be NULL.  A segment whose data hold a NaN or
+ * an infinity gets a power that is not finite (NaN with idx -1 when a cell
+ * is not a number); it takes no part in Eq. 6 and never crosses.  Among
+ * cells equal to within the 19 kept mantissa bits the lowest index wins
+ * within one (rate, SBD sub-grid); across sub-grids the float32 search keeps
+ * the sub-grid whose largest cell is largest in all bits. */
 frbx_status frbx_get_power_cube(const frbx_ctx *ctx, float *power, int32_t *idx,
                                 int64_t cap, int64_t *n);
 

@@ -375,6 +375,21 @@ __device__ __forceinline__ void mbd_column_peak(const float2 (&z)[MB], int r, in
   }
 }
 
+// Largest |G|^2 of one MBD column into blk, as float bits: |G|^2 >= 0
+// orders like its bits, and a cell that is not a number outranks every
+// number (its bits are above those of +inf).
+template <int MB>
+__device__ __forceinline__ void mbd_column_max(const float2 (&z)[MB], unsigned &blk) {
+  unsigned m = blk;
+  static_for<0, MB / 2>([&](auto kk) {
+    constexpr int ka = 2 * decltype(kk)::value, kb = ka + 1;
+    const float va = z[ka].x * z[ka].x + z[ka].y * z[ka].y;
+    const float vb = z[kb].x * z[kb].x + z[kb].y * z[kb].y;
+    m = max(m, max(__float_as_uint(va), __float_as_uint(vb)));
+  });
+  blk = m;
+}
+
 // CL (compact lattice): every IF sits at a lattice position below MB once
 // the positions are shifted by a common offset (which changes only the phase
 // of G, not |G|).  The first MBD pass then has one non-zero input per lane
@@ -388,7 +403,8 @@ __device__ __forceinline__ void mbd_column_peak(const float2 (&z)[MB], int r, in
 // reads and transforms only those rows (a kernel specialised to the IF
 // lattice when the search starts; the same sums).
 template <int J, int M, bool DUMP, bool CL, bool LIST = false, unsigned ROWS = 0u>
-__global__ __launch_bounds__(kBlock) void fringe_kernel(FringeArgs a) {
+__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(J <= 64 && !DUMP && !LIST ? 3 : 1)))
+void fringe_kernel(FringeArgs a) {
   using S = FringeShape<J, M>;
   constexpr int JA = S::JA, JB = S::JB, MA = S::MA, MB = S::MB, G = S::G, COLS = S::COLS;
   constexpr unsigned RMASK = ROWS ? ROWS : (MA >= 32 ? ~0u : (1u << MA) - 1u);
@@ -466,86 +482,163 @@ __global__ __launch_bounds__(kBlock) void fringe_kernel(FringeArgs a) {
 
   float best_v = -1.0f;
   int32_t best_i = 0x7fffffff;
+  float2 y[JA];
 
-  for (int r = 0; r < R; ++r) {
-    float2 y[JA];
+  auto sums = [&](int r) {
     if constexpr (LIST)
       segment_sum_direct<JA, JB>(y, a, lb, ld, k0, rph, r, N, J, l, R, s_p1, n1, i2s);
     else
       segment_sum<JA, JB>(y, wd, rph, r, N, J, l, R, s_p1, n1, i2s);
-
-    for (int c = 0; c < P; ++c) {
-      __syncthreads();
-      sbd_pass1<JA, JB>(y, a.pre_sbd, TW, Sc, c, P, PJ, s_p1, n1, i2s);
-      __syncthreads();
-      // SBD pass 2: JB-point DFT over i2 -> X[n][a = k1 + JA k2], the SBD
-      // bin s' = c + P a of the standard (unshifted) transform.
-      for (int v = t; v < N * JA; v += kBlock) {
-        const int n2 = v / JA, k1 = v - (v / JA) * JA;
-        float2 z[JB];
-        static_for<0, JB>([&](auto i) {
-          constexpr int ii = decltype(i)::value;
-          z[ii] = Sc[(n2 * JA + k1) * (JB + 1) + ii];
-        });
-        dft<JB>(z);
-        const int xrow = CL ? a.mbd_pos[n2] : n2;
-        static_for<0, JB>([&](auto k) {
-          constexpr int kk = decltype(k)::value;
-          X[xrow * XS + k1 + JA * kk] = z[kk];
-        });
+  };
+  // SBD transform of sub-grid c -> X
+  auto sbd = [&](int c) {
+    __syncthreads();
+    sbd_pass1<JA, JB>(y, a.pre_sbd, TW, Sc, c, P, PJ, s_p1, n1, i2s);
+    __syncthreads();
+    // SBD pass 2: JB-point DFT over i2 -> X[n][a = k1 + JA k2], the SBD
+    // bin s' = c + P a of the standard (unshifted) transform.
+    for (int v = t; v < N * JA; v += kBlock) {
+      const int n2 = v / JA, k1 = v - (v / JA) * JA;
+      float2 z[JB];
+      static_for<0, JB>([&](auto i) {
+        constexpr int ii = decltype(i)::value;
+        z[ii] = Sc[(n2 * JA + k1) * (JB + 1) + ii];
+      });
+      dft<JB>(z);
+      const int xrow = CL ? a.mbd_pos[n2] : n2;
+      static_for<0, JB>([&](auto k) {
+        constexpr int kk = decltype(k)::value;
+        X[xrow * XS + k1 + JA * kk] = z[kk];
+      });
+    }
+    __syncthreads();
+  };
+  // MBD transform of every SBD column of sub-grid c (rate r); FIND: the
+  // cells' keys and the running (value, packed index) of the lane, else
+  // only the largest |G|^2 (float bits) into blk
+  auto mbd = [&](int r, int c, auto find_tag, unsigned &blk) {
+    constexpr bool FIND = decltype(find_tag)::value != 0;
+    auto column = [&](const float2 (&z)[MB], int col) {
+      if constexpr (FIND)
+        mbd_column_peak<M, MA, MB, DUMP>(z, r, c, col, gl, P, PJ, a.dump, best_v, best_i);
+      else
+        mbd_column_max<MB>(z, blk);
+    };
+    if constexpr (CL) {
+      // compact lattice: z[i2] = X(position i2) w_M^(i2 k1), MB-point DFT
+      for (int a0 = 0; a0 < J; a0 += COLS) {
+        const int col = a0 + grp;
+        if (col < J && m_p2) {
+          float2 z[MB];
+          z[0] = X[col];
+          static_for<1, MB>([&](auto i) {
+            constexpr int ii = decltype(i)::value;
+            z[ii] = cmul(X[ii * XS + col], twm[ii]);
+          });
+          dft<MB>(z);
+          column(z, col);
+        }
       }
-      __syncthreads();
-
-      if constexpr (CL) {
-        // compact lattice: z[i2] = X(position i2) w_M^(i2 k1), MB-point DFT
-        for (int a0 = 0; a0 < J; a0 += COLS) {
-          const int col = a0 + grp;
-          if (col < J && m_p2) {
-            float2 z[MB];
-            z[0] = X[col];
-            static_for<1, MB>([&](auto i) {
+    } else {
+      // MBD over the IF lattice, one column a of this SBD tile per group.
+      // Unrolled by 4: the columns' LDS offsets become immediates.
+#pragma unroll 4
+      for (int a0 = 0; a0 < J; a0 += COLS) {
+        const int col = a0 + grp;
+        if (col < J) {
+          if (m_p1) {
+            float2 x[MA];
+            static_for<0, MA>([&](auto i) {
               constexpr int ii = decltype(i)::value;
-              z[ii] = cmul(X[ii * XS + col], twm[ii]);
+              if constexpr ((RMASK >> ii) & 1u) x[ii] = X[rowoff[ii] + col];
+              else x[ii] = make_float2(0.f, 0.f);
+            });
+            dft_masked<MA, RMASK>(x);
+            static_for<0, MA>([&](auto k) {
+              constexpr int kk = decltype(k)::value;
+              // w_M^(i2 k1) is 1 at k1 = 0
+              Sg[kk * MB + (gl ^ (kk & (MB - 1)))] = kk == 0 ? x[0] : cmul(x[kk], twm[kk]);
+            });
+          }
+          wave_lds_sync();
+          if (m_p2) {
+            float2 z[MB];
+            static_for<0, MB>([&](auto i) {
+              constexpr int ii = decltype(i)::value;
+              z[ii] = Sg[gl * MB + (ii ^ (gl & (MB - 1)))];
             });
             dft<MB>(z);
-            mbd_column_peak<M, MA, MB, DUMP>(z, r, c, col, gl, P, PJ, a.dump, best_v, best_i);
+            column(z, col);
           }
-        }
-      } else {
-        // MBD over the IF lattice, one column a of this SBD tile per group.
-        // Unrolled by 4: the columns' LDS offsets become immediates.
-#pragma unroll 4
-        for (int a0 = 0; a0 < J; a0 += COLS) {
-          const int col = a0 + grp;
-          if (col < J) {
-            if (m_p1) {
-              float2 x[MA];
-              static_for<0, MA>([&](auto i) {
-                constexpr int ii = decltype(i)::value;
-                if constexpr ((RMASK >> ii) & 1u) x[ii] = X[rowoff[ii] + col];
-                else x[ii] = make_float2(0.f, 0.f);
-              });
-              dft_masked<MA, RMASK>(x);
-              static_for<0, MA>([&](auto k) {
-                constexpr int kk = decltype(k)::value;
-                Sg[kk * MB + (gl ^ (kk & (MB - 1)))] = cmul(x[kk], twm[kk]);
-              });
-            }
-            wave_lds_sync();
-            if (m_p2) {
-              float2 z[MB];
-              static_for<0, MB>([&](auto i) {
-                constexpr int ii = decltype(i)::value;
-                z[ii] = Sg[gl * MB + (ii ^ (gl & (MB - 1)))];
-              });
-              dft<MB>(z);
-              mbd_column_peak<M, MA, MB, DUMP>(z, r, c, col, gl, P, PJ, a.dump, best_v, best_i);
-            }
-            wave_lds_sync();
-          }
+          wave_lds_sync();
         }
       }
     }
+  };
+
+  // ---- the search.  DUMP and LIST key every cell as they go.  Otherwise
+  // the scan keeps per lane only the largest |G|^2 (float bits) over each
+  // (rate, sub-grid) and the first (rate, sub-grid) holding the lane's
+  // maximum; the one holding the block's maximum is searched again with
+  // keys to find its cell.  A cell that is not a number then makes the
+  // segment's power NaN (index -1).
+  constexpr bool SCAN = !DUMP && !LIST;
+  unsigned scan_v = 0u;
+  int scan_rc = 0;
+  for (int r = 0; r < R; ++r) {
+    sums(r);
+    for (int c = 0; c < P; ++c) {
+      sbd(c);
+      unsigned blk = 0u;
+      if constexpr (!SCAN) {
+        mbd(r, c, Index<1>{}, blk);
+      } else {
+        mbd(r, c, Index<0>{}, blk);
+        if (blk > scan_v) {
+          scan_v = blk;
+          scan_rc = r * P + c;
+        }
+      }
+    }
+  }
+  if constexpr (SCAN) {
+    // block maximum and its (rate, sub-grid): larger value, then lower
+    // (rate, sub-grid)
+    for (int off = 32; off > 0; off >>= 1) {
+      const unsigned ov = __shfl_xor(scan_v, off, 64);
+      const int orc = __shfl_xor(scan_rc, off, 64);
+      if (ov > scan_v || (ov == scan_v && orc < scan_rc)) {
+        scan_v = ov;
+        scan_rc = orc;
+      }
+    }
+    if ((t & 63) == 0) {
+      red_v[t >> 6] = __uint_as_float(scan_v);
+      red_i[t >> 6] = scan_rc;
+    }
+    __syncthreads();
+    unsigned vmax = __float_as_uint(red_v[0]);
+    int rc = red_i[0];
+    for (int w = 1; w < kBlock / 64; ++w) {
+      const unsigned v = __float_as_uint(red_v[w]);
+      if (v > vmax || (v == vmax && red_i[w] < rc)) {
+        vmax = v;
+        rc = red_i[w];
+      }
+    }
+    if (vmax > 0x7F800000u) {   // a cell that is not a number (non-finite input)
+      if (t == 0) {
+        const int64_t o = int64_t(dl) * a.seg_total + seg;
+        a.power[o] = __builtin_nanf("");
+        a.pidx[o] = -1;
+      }
+      return;
+    }
+    const int r = rc / P, c = rc - (rc / P) * P;
+    sums(r);
+    sbd(c);   // its first barrier also ends the reads of red_* above
+    unsigned unused = 0u;
+    mbd(r, c, Index<1>{}, unused);
   }
 
   // ---- block reduction: larger |G|^2 wins, ties -> lower packed index
