@@ -490,7 +490,7 @@ def run_form(args, wl, V, prec, dev, truth, budget, reserve_after, headline):
         extra["mbd_products"] = "three real per complex" if k3 else "four real per complex"
         extra["method_flops_per_cell"] = 8 * N
         kern = "fringe_mfma_kernel"
-        if base_prec == "f16" and J in SBD_GEMM_CHANNELS:
+        if base_prec == "f16" and srch.get("sbd_mfma") and J in SBD_GEMM_CHANNELS:
             fpc += 8 * N * J / M
             extra["method_flops_per_cell"] += 8 * N * J / M
             kern = "fringe_gemm_kernel"
@@ -642,7 +642,7 @@ def run_stream(args):
     else:
         fpc = (6 if three_real_products(args.precision, N, J) else 8) * N * (3 if args.precision == "f16x3" else 1)
         bound, peak, kern = "mfma", PEAK_FP16_MFMA_TFLOPS, "fringe_mfma_kernel"
-        if args.precision == "f16" and J in SBD_GEMM_CHANNELS:
+        if args.precision == "f16" and srch.get("sbd_mfma") and J in SBD_GEMM_CHANNELS:
             fpc += 8 * N * J / M
             kern = "fringe_gemm_kernel"
     ach = units * cells_seg * fpc / (avg * 1e-3) / 1e12 if avg > 0 else 0.0

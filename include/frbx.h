@@ -186,12 +186,9 @@ frbx_status frbx_set_tile_budget(frbx_ctx *ctx, int64_t bytes);
  *                       float16 high/low split of both operands, float32
  *                       accumulation): products good to ~2^-21 relative.
  *   FRBX_PREC_F16       one float16 product (inputs and DFT matrices
- *                       rounded once to float16, float32 accumulation), and
- *                       for n_chan <= 64 the SBD transform on the matrix
- *                       cores too: per SBD sub-grid a real-embedded J-point
- *                       DFT of the rotated segment sums (float32 segment
- *                       sums, float16 operands); for n_chan >= 128 the SBD
- *                       transform runs as in FRBX_PREC_F16X3.
+ *                       rounded once to float16, float32 accumulation); the
+ *                       SBD transform as in FRBX_PREC_F16X3, or on the
+ *                       matrix cores too (frbx_set_sbd_matrix_cores).
  * The matrix-core forms need n_mbd = 256, n_chan >= 16 and n_if <= 32
  * (FRBX_E_INVAL at frbx_run otherwise); their operands are scaled by a
  * power of two chosen from the largest input component so that float16
@@ -200,6 +197,15 @@ frbx_status frbx_set_tile_budget(frbx_ctx *ctx, int64_t bytes);
 typedef enum { FRBX_PREC_F32 = 0, FRBX_PREC_F16X3 = 1, FRBX_PREC_F16 = 2 } frbx_precision;
 
 frbx_status frbx_set_precision(frbx_ctx *ctx, int32_t precision);
+
+/* FRBX_PREC_F16 with n_chan <= 64: enable = 1 runs the SBD transform on the
+ * matrix cores as well: per SBD sub-grid a real-embedded J-point DFT GEMM of
+ * the rotated segment sums (float32 sums, float16 operands), eight waves per
+ * segment.  Default 0 (the float32 SBD transform of FRBX_PREC_F16X3, which
+ * measured faster: 110 against 122 ms per launch on the VGOS-shaped
+ * workload).  Same accuracy bar either way; takes effect at the next
+ * frbx_run. */
+frbx_status frbx_set_sbd_matrix_cores(frbx_ctx *ctx, int enable);
 
 /* Kernel specialisation (not a step of the paper).  In FRBX_PREC_F32,
  * when the IF lattice of Eq. 5 is not compact (the general form of the

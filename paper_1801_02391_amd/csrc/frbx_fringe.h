@@ -263,18 +263,17 @@ __device__ __forceinline__ void segment_sum(float2 (&y)[JA], const float2 *wd, c
   const int NJ = N * J;
   const float2 *src = wd + n1 * J + i2s;
   const float2 *ph = rph + (r * N + n1) * l;
-  // the rate test outside the AP loop
-  if (R > 1) {
-    for (int u = 0; u < l; ++u) {
+  // (the rate test inside the AP loop: with it outside, the compiler issues
+  // the loads of an AP one at a time, each waited for)
+  for (int u = 0; u < l; ++u) {
+    if (R > 1) {
       const float2 p = ph[u];
       static_for<0, JA>([&](auto i) {
         constexpr int ii = decltype(i)::value;
         const float2 v = src[int64_t(u) * NJ + JB * ii];
         y[ii] = cadd(y[ii], cmul(v, p));
       });
-    }
-  } else {
-    for (int u = 0; u < l; ++u) {
+    } else {
       static_for<0, JA>([&](auto i) {
         constexpr int ii = decltype(i)::value;
         y[ii] = cadd(y[ii], src[int64_t(u) * NJ + JB * ii]);
@@ -576,13 +575,16 @@ void fringe_kernel(FringeArgs a) {
     }
   };
 
-  // ---- the search.  DUMP and LIST key every cell as they go.  Otherwise
-  // the scan keeps per lane only the largest |G|^2 (float bits) over each
+  // ---- the search.  DUMP and LIST key every cell as they go, and so does
+  // every search with fewer than 8 (rate, sub-grid) pairs, where searching
+  // one of them again would cost more than keying saves.  Otherwise the
+  // scan keeps per lane only the largest |G|^2 (float bits) over each
   // (rate, sub-grid) and the first (rate, sub-grid) holding the lane's
   // maximum; the one holding the block's maximum is searched again with
   // keys to find its cell.  A cell that is not a number then makes the
   // segment's power NaN (index -1).
   constexpr bool SCAN = !DUMP && !LIST;
+  const bool scan = SCAN && R * P >= 8;
   unsigned scan_v = 0u;
   int scan_rc = 0;
   for (int r = 0; r < R; ++r) {
@@ -590,7 +592,7 @@ void fringe_kernel(FringeArgs a) {
     for (int c = 0; c < P; ++c) {
       sbd(c);
       unsigned blk = 0u;
-      if constexpr (!SCAN) {
+      if (!scan) {
         mbd(r, c, Index<1>{}, blk);
       } else {
         mbd(r, c, Index<0>{}, blk);
@@ -601,7 +603,7 @@ void fringe_kernel(FringeArgs a) {
       }
     }
   }
-  if constexpr (SCAN) {
+  if (scan) {
     // block maximum and its (rate, sub-grid): larger value, then lower
     // (rate, sub-grid)
     for (int off = 32; off > 0; off >>= 1) {

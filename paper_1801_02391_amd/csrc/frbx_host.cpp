@@ -78,6 +78,7 @@ struct frbx_ctx {
   size_t list_cap = 0;
   int32_t mbd_shift = -1;        // that shift, -1 for the general form
   int specialise = 1;            // float32 general form: kernel compiled for the lattice's rows
+  int sbd_mfma = 0;              // float16 form: SBD transform on the matrix cores as well
   unsigned rows_mask = 0;        // rows of the kernel in use (0: the statically built kernel)
   hipFunction_t rows_fn = nullptr;
   std::string rows_note;         // why the specialised kernel is not in use
@@ -366,10 +367,12 @@ float2 cis_cycles(double x) {
                      static_cast<float>(-std::sin(kTwoPi * r)));
 }
 
-// The float16 form runs both transforms on the matrix cores where the
-// shape allows (n_chan <= 64); otherwise its SBD stays on the vector ALUs.
+// The float16 form runs both transforms on the matrix cores when asked to
+// (frbx_set_sbd_matrix_cores) and the shape allows it (n_chan <= 64);
+// otherwise its SBD stays on the vector ALUs.
 bool use_gemm(const frbx_ctx *c) {
-  return c->precision == FRBX_PREC_F16 && frbx::fringe_gemm_supported(c->J, c->n_mbd, c->N, c->sbd_pad);
+  return c->sbd_mfma && c->precision == FRBX_PREC_F16 &&
+         frbx::fringe_gemm_supported(c->J, c->n_mbd, c->N, c->sbd_pad);
 }
 
 // The matrix-core fringe launch of the current precision (both transforms
@@ -1013,6 +1016,13 @@ frbx_status frbx_set_precision(frbx_ctx *c, int32_t precision) {
   c->precision = precision;
   c->dirty = true;
   c->have = false;
+  return FRBX_OK;
+}
+
+frbx_status frbx_set_sbd_matrix_cores(frbx_ctx *c, int enable) {
+  if (!c) return FRBX_E_INVAL;
+  c->sbd_mfma = enable ? 1 : 0;
+  c->dirty = true;
   return FRBX_OK;
 }
 

@@ -74,6 +74,7 @@ _SIGS = {
     "frbx_set_precision": ([_P, C.c_int32], C.c_int),
     "frbx_set_tile_budget": ([_P, C.c_int64], C.c_int),
     "frbx_set_specialisation": ([_P, C.c_int], C.c_int),
+    "frbx_set_sbd_matrix_cores": ([_P, C.c_int], C.c_int),
     "frbx_get_specialisation": ([_P, C.POINTER(C.c_uint32), C.POINTER(C.c_char_p)], C.c_int),
     "frbx_run": ([_P], C.c_int),
     "frbx_run_cube_noalloc": ([_P, _P, _P, C.c_int64, C.POINTER(C.c_int64)], C.c_int),
@@ -270,6 +271,7 @@ class Search:
         self._chk(L.frbx_set_precision(h, PRECISIONS[prec] if isinstance(prec, str) else int(prec)),
                   "set_precision")
         self._chk(L.frbx_set_recheck(h, float(search.get("recheck_band", 0.0))), "set_recheck")
+        self._chk(L.frbx_set_sbd_matrix_cores(h, 1 if search.get("sbd_mfma", False) else 0), "set_sbd_matrix_cores")
         if tau0_us is not None or phi0_rad is not None:
             t = None if tau0_us is None else np.ascontiguousarray(tau0_us, dtype=np.float64)
             p = None if phi0_rad is None else np.ascontiguousarray(phi0_rad, dtype=np.float64)

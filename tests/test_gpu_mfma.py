@@ -53,9 +53,13 @@ def test_f16x3_matches_oracle_at_float32_bar(J, N, R):
     compare_crossings(gpu["crossings"], ora["crossings"], 3.0)
 
 
-@pytest.mark.parametrize("J,N,R", [(64, 32, 2), (32, 8, 1), (16, 12, 3), (128, 20, 1)])
-def test_f16_storage_and_products_within_1e3(J, N, R):
+@pytest.mark.parametrize("J,N,R,sbd_mfma", [(64, 32, 2, False), (64, 32, 2, True), (32, 8, 1, False),
+                                            (32, 8, 1, True), (16, 12, 3, True), (128, 20, 1, False)])
+def test_f16_storage_and_products_within_1e3(J, N, R, sbd_mfma):
+    """The f16 form with its SBD transform in float32 (default) and on the
+    matrix cores (frbx_set_sbd_matrix_cores) against the oracle."""
     wl = _wl(J, N, R, seed_id=95 + J, precision="f16")
+    wl["search"]["sbd_mfma"] = sbd_mfma
     V, _ = W.generate(wl)
     H = W.to_complex32(V)
     Vq = W.from_complex32(H)          # the stored values, exactly
@@ -68,7 +72,7 @@ def test_f16_storage_and_products_within_1e3(J, N, R):
     P, I = s.power_cube()
     ora = O.search(Vq, wl["layout"], wl["search"])
     err = _check(dict(P=P, I=I), ora, wl["layout"]["n_baselines"], wl["search"]["n_dm"], 1e-3, 4e-3)
-    note(f"f16 J={J} N={N}: max power rel err {err:.2e}")
+    note(f"f16 J={J} N={N} sbd on matrix cores {sbd_mfma}: max power rel err {err:.2e}")
 
 
 def test_mfma_grid_dump_elementwise():
@@ -103,14 +107,16 @@ def test_f16x3_detections_equal_f32_path():
     assert [key(d) for d in a["candidates"]] == [key(d) for d in b["candidates"]]
 
 
-@pytest.mark.parametrize("J,N", [(64, 32), (16, 12)])
-def test_f16_grid_dump_elementwise(J, N):
-    """Every cell of one segment's |G|^2 from the f16 form (SBD and MBD
-    transforms both on the matrix cores) against the oracle's grid on the
-    same stored complex32 values, relative to the grid maximum."""
+@pytest.mark.parametrize("J,N,sbd_mfma", [(64, 32, True), (16, 12, True), (64, 32, False)])
+def test_f16_grid_dump_elementwise(J, N, sbd_mfma):
+    """Every cell of one segment's |G|^2 from the f16 form (the MBD transform,
+    and with sbd_mfma the SBD transform too, on the matrix cores) against the
+    oracle's grid on the same stored complex32 values, relative to the grid
+    maximum."""
     import torch
     from paper_1801_02391_amd import frbx
     wl = _wl(J, N, 2, K=120, windows=(3, 8), n_dm=2, seed_id=97 + J, precision="f16")
+    wl["search"]["sbd_mfma"] = sbd_mfma
     V, _ = W.generate(wl)
     H = W.to_complex32(V)
     Vq = W.from_complex32(H)
