@@ -413,7 +413,7 @@ frbx_status prepare(frbx_ctx *c) {
       }
       return true;
     };
-    while (g < D && g < 64 && fits(g + 1)) ++g;
+    while (g < D && g < frbx::kDedispMaxGroup && fits(g + 1)) ++g;
     c->dd_group = g;
   }
   const int nw = int(c->windows.size());

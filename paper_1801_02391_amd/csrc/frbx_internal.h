@@ -54,6 +54,7 @@ struct DedisperseArgs {
 constexpr int kDedispCh = 16;
 constexpr int kDedispAp = 256;
 constexpr int kDedispSpread = 128;
+constexpr int kDedispMaxGroup = 64;   // DM trials per staged tile at most
 
 // Fringe search of every segment of one baseline and DM tile (Sec. 2.3,
 // Eq. 5 with the rate term of Eq. 4; Sec. 5.1): segment sums of W with rate

@@ -60,16 +60,19 @@ namespace {
 // ---------------------------------------------------------------- kernels
 
 // One work-group dedisperses a tile of 16 channels x 256 APs for a group of
-// DM trials: each channel's input span (the 128 APs shifted by the group's
+// DM trials: each channel's input span (the 256 APs shifted by the group's
 // smallest offset, plus the offset spread of the group) is read once,
-// coalesced, into LDS; every trial of the group then writes its 128
-// AP-major spectra from the staged span (16 channels = 128 contiguous bytes
-// per AP), with the Eq. 5 calibration applied on the way.
+// coalesced, into LDS, with the group's offsets relative to its first
+// trial; every trial of the group then writes its 256 AP-major spectra from
+// the staged span (16 channels = 128 contiguous bytes per AP), with the
+// Eq. 5 calibration applied on the way.  The write loop reads nothing from
+// global memory: a load there would make each wave wait for its earlier
+// stores to complete (one counter covers both on this GPU).
 template <bool F16>
 __global__ __launch_bounds__(kBlock) void dedisperse_kernel(DedisperseArgs a) {
   constexpr int SW = kDedispAp + kDedispSpread + 1;   // staged APs per channel (+1 pad)
   __shared__ float2 tile[kDedispCh][SW];
-  __shared__ int32_t dks[kDedispCh];
+  __shared__ int32_t shs[kDedispMaxGroup][kDedispCh];  // offset of trial g0 + j minus trial g0's
   const int64_t kt = int64_t(blockIdx.x) * kDedispAp;
   const int ct = blockIdx.y * kDedispCh;
   const int g0 = blockIdx.z * a.group;                  // first trial of the group (tile-local)
@@ -77,9 +80,10 @@ __global__ __launch_bounds__(kBlock) void dedisperse_kernel(DedisperseArgs a) {
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
   const int32_t *dk0 = a.dk + int64_t(a.d0 + g0) * a.nj;
   const int32_t *dk1 = a.dk + int64_t(a.d0 + g0 + ng - 1) * a.nj;
-  if (threadIdx.x < kDedispCh) {
-    const int c = ct + threadIdx.x;
-    dks[threadIdx.x] = c < a.nj ? dk0[c] : 0;
+  for (int x = threadIdx.x; x < ng * kDedispCh; x += kBlock) {
+    const int j = x / kDedispCh, i = x - j * kDedispCh;
+    const int c = ct + i;
+    shs[j][i] = c < a.nj ? a.dk[int64_t(a.d0 + g0 + j) * a.nj + c] - dk0[c] : 0;
   }
   // stage: wave w loads channels w, w + 4, ...; frames base .. base + span
   for (int i = w; i < kDedispCh; i += kBlock / 64) {
@@ -98,13 +102,22 @@ __global__ __launch_bounds__(kBlock) void dedisperse_kernel(DedisperseArgs a) {
   const int cl = lane & (kDedispCh - 1);
   const int c = ct + cl;
   const float2 cal = c < a.nj ? a.cal[c] : make_float2(0.f, 0.f);
-  const int kr = threadIdx.x / kDedispCh;                // 0..7
+  const int kr = threadIdx.x / kDedispCh;                // 0..15
+  // full tiles (all but the last AP tile) store without a bounds test, so
+  // that the staged reads of several APs are issued together
+  const bool full = kt + kDedispAp <= a.k_eff && ct + kDedispCh <= a.nj;
   for (int j = 0; j < ng; ++j) {
-    const int shift = c < a.nj ? a.dk[int64_t(a.d0 + g0 + j) * a.nj + c] - dks[cl] : 0;
+    const int shift = shs[j][cl];
     float2 *outd = a.out + int64_t(g0 + j) * a.k_eff * a.nj;
-    for (int kk = kr; kk < kDedispAp; kk += kBlock / kDedispCh) {
-      const int64_t k = kt + kk;
-      if (c < a.nj && k < a.k_eff) outd[k * a.nj + c] = cmul(tile[cl][kk + shift], cal);
+    if (full) {
+#pragma unroll 8
+      for (int kk = kr; kk < kDedispAp; kk += kBlock / kDedispCh)
+        outd[(kt + kk) * a.nj + c] = cmul(tile[cl][kk + shift], cal);
+    } else {
+      for (int kk = kr; kk < kDedispAp; kk += kBlock / kDedispCh) {
+        const int64_t k = kt + kk;
+        if (c < a.nj && k < a.k_eff) outd[k * a.nj + c] = cmul(tile[cl][kk + shift], cal);
+      }
     }
   }
 }
@@ -1103,7 +1116,7 @@ __global__ __launch_bounds__(kBlock) void refine_kernel(RefineArgs a) {
 // ---------------------------------------------------------------- launchers
 hipError_t launch_dedisperse(const DedisperseArgs &a, hipStream_t s) {
   (void)hipGetLastError();
-  if (a.group < 1) return hipErrorInvalidValue;
+  if (a.group < 1 || a.group > kDedispMaxGroup) return hipErrorInvalidValue;
   dim3 grid(unsigned((a.k_eff + kDedispAp - 1) / kDedispAp), unsigned((a.nj + kDedispCh - 1) / kDedispCh),
             unsigned((a.n_dt + a.group - 1) / a.group));
   if (a.in_f16)
