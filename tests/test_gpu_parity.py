@@ -103,6 +103,28 @@ def test_search_matches_oracle_end_to_end(J, M, N, R, P, monkeypatch):
     assert [g["n_baselines"] for g in gpu["groups"]] == [g["n_baselines"] for g in ogroups]
 
 
+def test_dedispersion_tiles_full_and_ragged():
+    """Every kind of dedispersion tile: 24 channels (one full and one partial
+    16-channel tile) over 700 APs (two full 256-AP tiles and a partial one),
+    the three DM trials staged as one group: power cube, indices and Eq. 6
+    statistics against the oracle."""
+    wl = _tiny(8, 16, N=3, R=1, P=4, K=700, n_dm=3, dm_step=60.0, seed_id=91)
+    V, _ = W.generate(wl)
+    gpu = run_gpu(wl, V)
+    note("oracle")
+    ora = O.search(V, wl["layout"], wl["search"])
+    dk_max = ora["grids"]["dk_max"]
+    assert gpu["seg"]["dk_max"] == dk_max and 700 - dk_max > 512
+    segs = ora["grids"]["segs"]
+    B, D = wl["layout"]["n_baselines"], wl["search"]["n_dm"]
+    Po, Io, S2o = oracle_cube(ora, B, D, segs)
+    compare_powers(gpu["P"], gpu["I"], Po, Io, S2o, "cube")
+    nw = len(segs)
+    for (b, d, wi), (mu, sd) in ora["stats"].items():
+        row = (b * D + d) * nw + wi
+        assert gpu["mean"][row] == pytest.approx(mu, rel=2e-5)
+
+
 def test_zero_input_and_degenerate_single_if():
     """All-zero spectra: every power is 0 with the lowest packed index 0 and
     no crossings; one IF: the MBD axis is flat and the lowest MBD bin wins."""
