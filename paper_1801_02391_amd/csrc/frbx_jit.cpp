@@ -41,7 +41,11 @@ void compile(int J, int M, unsigned rows, JitEntry &e) {
     e.err = "hiprtcCreateProgram failed";
     return;
   }
-  hiprtcAddNameExpression(prog, expr.c_str());
+  if (hiprtcAddNameExpression(prog, expr.c_str()) != HIPRTC_SUCCESS) {
+    e.err = "hiprtcAddNameExpression failed";
+    hiprtcDestroyProgram(&prog);
+    return;
+  }
   // the options of the static build: gfx950, packed FP32 kept out
   const char *opts[] = {"--offload-arch=gfx950", "-O3",      "-std=c++17",       "-ffp-contract=fast",
                         "-Xclang",               "-target-feature", "-Xclang", "-packed-fp32-ops"};
