@@ -94,3 +94,25 @@ def test_work_of_the_pruned_first_pass():
     full = bench.fringe_flops_per_cell(32, 64, 4, 256)
     pruned = bench.fringe_flops_per_cell(32, 64, 4, 256, 0, 0x40D1)
     assert abs((full - pruned) * 65536 - 256 * 10240 * (1 - (16 * 216 + 16 * 320) / (32 * 320))) < 1e-6
+
+
+def test_measured_traffic_is_keyed_to_the_kernel_code(tmp_path, monkeypatch):
+    """The bench reports counter-measured HBM bytes only for the workload they
+    were taken on and only while the kernel code hashes as it did then; the
+    hash ignores comments and blank lines."""
+    sys.path.insert(0, ROOT)
+    import bench
+    src = tmp_path / "k.hip"
+    src.write_text("int x;  // a note\n\nint y;\n")
+    monkeypatch.setattr(bench, "KERNEL_SOURCES", [str(src)])
+    sha = bench.kernel_code_sha256()
+    src.write_text("// another note\nint x;\nint y;   // changed commentary\n")
+    assert bench.kernel_code_sha256() == sha
+    traffic = tmp_path / "traffic.txt"
+    traffic.write_text(f"# comment = ignored\nkernels_sha256 = {sha}\nfringe_kernel = 12345\n")
+    monkeypatch.setattr(bench, "TRAFFIC_FILE", str(traffic))
+    assert bench.measured_traffic("fringe_kernel", "vgos-6bl-32x64-20000") == 12345.0
+    assert bench.measured_traffic("fringe_kernel", "single-1bl-8x32-1000") is None
+    assert bench.measured_traffic("dedisperse_kernel", "vgos-6bl-32x64-20000") is None
+    src.write_text("int x;\nint y = 1;\n")
+    assert bench.measured_traffic("fringe_kernel", "vgos-6bl-32x64-20000") is None
